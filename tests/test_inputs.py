@@ -1,0 +1,73 @@
+"""Pins of the seeded input generator (turbulent fields and particle draws)."""
+
+import math
+
+import numpy as np
+
+from paper_2602_23434_amd import inputs
+
+
+def test_turbulent_fields_properties():
+    n = (32, 32, 32)
+    f = inputs.turbulent_fields(n, inputs.SEED_B + 1, inputs.SEED_V + 1)
+    E, B, vg = f["E"], f["B"], f["vg"]
+    dB = B.copy()
+    dB[2] -= 1.0
+    # rms normalisation of dB and v
+    assert abs(math.sqrt(np.mean((dB * dB).sum(axis=0))) - 0.5) < 1e-12
+    assert abs(math.sqrt(np.mean((vg * vg).sum(axis=0))) - 0.1) < 1e-12
+    # E = -v x B is perpendicular to B cell by cell
+    edotb = (E * B).sum(axis=0)
+    scale = np.sqrt((E * E).sum(axis=0) * (B * B).sum(axis=0))
+    assert np.abs(edotb).max() <= 1e-15 * scale.max() * 10
+    # divergence-free in Fourier space: m . B_hat(m) = 0
+    for fld in (B, vg):
+        hat = [np.fft.fftn(fld[c]) for c in range(3)]
+        kz, ky, kx = np.meshgrid(*[np.fft.fftfreq(a, 1.0 / a) for a in (n[2], n[1], n[0])], indexing="ij")
+        div = kx * hat[0] + ky * hat[1] + kz * hat[2]
+        mag = np.sqrt(kx ** 2 + ky ** 2 + kz ** 2) * np.sqrt(sum(np.abs(h) ** 2 for h in hat))
+        assert np.abs(div).max() <= 1e-12 * mag.max()
+    # no power outside 1 <= |m| <= N/4
+    hat = np.fft.fftn(dB[0])
+    kz, ky, kx = np.meshgrid(*[np.fft.fftfreq(a, 1.0 / a) for a in n], indexing="ij")
+    km = np.sqrt(kx ** 2 + ky ** 2 + kz ** 2)
+    assert np.abs(hat[km > 8.0 + 1e-9]).max() < 1e-9 * np.abs(hat).max()
+
+
+def test_generator_is_deterministic():
+    a = inputs.turbulent_box(n=16, npart=1000)
+    b = inputs.turbulent_box(n=16, npart=1000)
+    for k in ("E", "B", "vg"):
+        assert np.array_equal(a.boxes[0].fields[k], b.boxes[0].fields[k])
+    pa, pb = a.items[0].particles, b.items[0].particles
+    assert np.array_equal(pa.x, pb.x) and np.array_equal(pa.u, pb.u)
+    assert pa.id.tolist() == list(range(1000))
+
+
+def test_particle_draws():
+    wl = inputs.gyration_2d()
+    p = wl.items[0].particles
+    assert p.n == 4096
+    v = p.u / np.sqrt(1 + (p.u * p.u).sum(axis=0))
+    assert np.abs(np.sqrt((v * v).sum(axis=0)) - 0.1).max() < 1e-15
+    assert (p.x[:2] >= 0).all() and (p.x[:2] < 32).all() and (p.x[2] == 0).all()
+    wl = inputs.turbulent_box(n=16, npart=200000)
+    p = wl.items[0].particles
+    v = p.u / np.sqrt(1 + (p.u * p.u).sum(axis=0))
+    assert abs(v.std() - 0.05) < 0.001
+    assert (p.x >= 0).all() and (p.x < 16).all()
+
+
+def test_clumps_and_batch_counts():
+    wl = inputs.clumped_box(n=32, npart=1 << 16, nclumps=4, sigma=2.0)
+    p = wl.items[0].particles
+    assert p.n == 1 << 16
+    assert (p.x >= 0).all() and (p.x < 32).all()
+    cells = np.floor(p.x).astype(np.int64)
+    occ = np.bincount(cells[0] + 32 * (cells[1] + 32 * cells[2]), minlength=32 ** 3)
+    assert occ.max() > 20 * occ.mean()
+    wl = inputs.batched(n_main=16, n_cr=1000, n_dust=500, n_tracer=100, n_small=8, n_boxes=4,
+                        small_lo=50, small_hi=2000)
+    counts = wl.notes["small_counts"]
+    assert len(wl.items) == 3 + 4 and all(50 <= c <= 2000 for c in counts)
+    assert [it.particles.n for it in wl.items[3:]] == counts
