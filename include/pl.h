@@ -1,0 +1,241 @@
+/*
+ * pl.h -- C ABI of libpl.so, the MI355X (gfx950) particle-update library.
+ *
+ * One step of the update, for every particle of every item passed in:
+ *   1. locate the particle's cell and TSC/CIC weights and gather the grid
+ *      fields there (the particles sample the fluid at their position, Sec. 2
+ *      after Eq. 1; the weights are the textbook CIC/TSC assignment functions);
+ *   2. advance it: relativistic Boris push for charged particles, exact
+ *      exponential drag towards the gas velocity for dust, two-stage
+ *      Runge-Kutta on the sampled gas velocity for passive tracers (Eq. 1,
+ *      the paper's Lagrangian particles, two RK sub-steps per step, Sec. 3.3);
+ *   3. deposit its moments (charge or mass density, current, force, energy
+ *      change) onto the grid at the new position with the same weights.
+ * A stable cell-tile counting sort groups particles by tile so the tiled
+ * kernels can stage fields and deposits in LDS.
+ *
+ * Conventions
+ * - Grid coordinates are in cell units: cell i spans [i, i+1), its centre is
+ *   i + 1/2, the box is [0, n) per dimension and periodic.  Grid arrays are
+ *   float64, cell-centred, flat index i + n[0]*(j + n[1]*k).
+ * - Equations of motion (code units, speed of light c):
+ *     charged:  du/dt = (q/m)(E + (u/gamma) x B),  gamma = sqrt(1 + |u|^2/c^2),
+ *               dx/dt = u/gamma
+ *     dust:     dv/dt = -(v - v_gas(x)) / t_stop,   dx/dt = v
+ *     tracer:   dx/dt = v_gas(x)                    (Eq. 1)
+ *   Positions advance by dt*v/dx per dimension.  The velocity passed in is
+ *   the one at the previous half step (leapfrog).
+ * - Deposited channels per unit cell volume dV = dx*dy(*dz), at the new
+ *   position:  rho = q w (dust: m w);  J = q w v;  F = m w du/dt (the momentum
+ *   change over the step divided by dt);  eng = m w c^2 dgamma/dt.
+ *
+ * Ownership and streams
+ * - Every particle, field and moment array is caller-owned DEVICE memory
+ *   (e.g. torch tensors' data_ptr()).  The library owns only the context and
+ *   the scratch it allocates in pl_part_init; no other call allocates.
+ * - All work is queued on the context's stream and is asynchronous; results
+ *   are ready after pl_part_sync() (or any later stream synchronisation).
+ * - One context per stream; calls on one context must not overlap.
+ *
+ * Errors
+ * - Every call returns a pl_status.  Argument errors are detected on the host
+ *   before any device work is queued and leave all data untouched.
+ * - Device-side conditions (a particle that moved a full cell or more in one
+ *   step, a non-finite or out-of-range particle coordinate) are latched in the
+ *   context and returned by the next pl_part_sync() as PL_ECFL / PL_ENONFINITE;
+ *   affected particles are still processed with wrapped, in-range indices.
+ */
+#ifndef PL_H
+#define PL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int pl_status;
+#define PL_OK            0
+#define PL_EINVAL        1   /* invalid argument (null/misaligned pointer, bad size or enum) */
+#define PL_ENOMEM        2   /* device or pinned-host allocation failed in pl_part_init */
+#define PL_EHIP          3   /* a HIP runtime call failed */
+#define PL_EUNSUPPORTED  4   /* valid request this build does not implement */
+#define PL_ECFL          5   /* a particle moved a full cell or more in one step */
+#define PL_ENONFINITE    6   /* a particle coordinate was non-finite or outside the grid */
+
+/* Storage / arithmetic form of the particles. */
+#define PL_F64         0   /* float64 absolute grid coordinates and velocities */
+#define PL_F32_OFFSET  1   /* packed uint32 cell + float32 offsets from the cell centre, float32 u */
+
+#define PL_CIC 1
+#define PL_TSC 2
+
+#define PL_LORENTZ 0       /* charged particle, relativistic Boris */
+#define PL_DUST    1       /* dust grain, drag towards the gas velocity */
+#define PL_TRACER  2       /* passive tracer of the gas velocity (Eq. 1) */
+
+#define PL_ALGO_PLAIN 0    /* one thread per particle, fields and deposits straight from/to HBM */
+#define PL_ALGO_TILED 1    /* per-tile LDS field stage and LDS deposit (needs pl_part_sort) */
+
+#define PL_KEY_TILE       0  /* sort by tile */
+#define PL_KEY_TILE_CELL  1  /* sort by tile, then by cell inside the tile (x fastest) */
+
+/* flags of pl_part_gather_push / pl_part_deposit */
+#define PL_FUSE_DEPOSIT  (1u << 0)  /* gather_push also deposits at the new positions */
+#define PL_ZERO_FIRST    (1u << 1)  /* zero the items' moment grids before depositing */
+#define PL_GRAPH         (1u << 2)  /* record the call's launches once as a hipGraph, replay afterwards */
+#define PL_SUMS          (1u << 3)  /* accumulate particle-side conservation sums (see pl_part_sums) */
+
+typedef struct pl_ctx pl_ctx;
+
+typedef struct {
+    int n[3];         /* cells per dimension (n[2] == 1 in 2D); each 1..1024 */
+    double dx[3];     /* cell size per dimension (> 0) */
+    int tile[3];      /* tile edge in cells (sort key, LDS tile); must divide n; tile[2] == 1 in 2D */
+} pl_box_desc;
+
+typedef struct {
+    int kind;         /* PL_LORENTZ, PL_DUST or PL_TRACER */
+    double q, m;      /* charge and mass per unit weight (m > 0) */
+    double weight;    /* weight of every particle when an item passes no weights */
+    double t_stop;    /* dust stopping time (> 0 for PL_DUST) */
+} pl_species_desc;
+
+typedef struct {
+    int ndim;                        /* 2 or 3, for every box of the context */
+    int prec;                        /* PL_F64 or PL_F32_OFFSET */
+    int shape;                       /* PL_CIC or PL_TSC */
+    int algo;                        /* PL_ALGO_PLAIN (PL_F64 only) or PL_ALGO_TILED */
+    int key_mode;                    /* PL_KEY_TILE or PL_KEY_TILE_CELL */
+    double c;                        /* speed of light in code units (> 0) */
+    int nboxes;
+    const pl_box_desc *boxes;        /* host array, copied */
+    int nspecies;
+    const pl_species_desc *species;  /* host array, copied */
+    int max_items;                   /* most items any one call passes (>= 1) */
+    int64_t max_np;                  /* most particles in any one item (sizes the sort scratch) */
+    int block;                       /* threads per block of the particle kernels (64..512, multiple of 64); 0 = default */
+    void *stream;                    /* hipStream_t for all work; NULL = the null stream */
+    const char *tune_cache;          /* nullable: file written by the autotuner (block, tile) */
+} pl_init_desc;
+
+/*
+ * Particles of one item, structure of arrays, two buffer sets: the sort reads
+ * set `cur` and writes set 1-cur, then flips `cur`.  Set 1-cur may be left
+ * NULL by callers that never sort.  Pointers are device pointers aligned to
+ * their element size.
+ */
+typedef struct {
+    int64_t n;              /* particle count, 0 <= n <= max_np, n < 2^31 */
+    int cur;                /* 0 or 1: the set holding the current state */
+    uint32_t *cell[2];      /* PL_F32_OFFSET: cell i | j<<10 | k<<20;  PL_F64: unused */
+    void *x[2][3];          /* PL_F64: double grid coordinates; PL_F32_OFFSET: float offsets in [-1/2, 1/2) */
+    void *u[2][3];          /* velocity (u = gamma v for charged particles), double or float */
+    void *w[2];             /* nullable: per-particle weights (double or float) */
+    uint64_t *id[2];        /* nullable: particle ids, carried through the sort */
+    void *fp[3];            /* nullable: per-particle force m w du/dt, written by gather_push, read by deposit */
+    int32_t *tile_start;    /* ntiles+1 first-particle offsets per tile, written by pl_part_sort;
+                               required by PL_ALGO_TILED */
+} pl_particles;
+
+typedef struct {
+    const double *E[3];     /* charged particles: electric field (the E of du/dt above) */
+    const double *B[3];     /* charged particles: magnetic field */
+    const double *vg[3];    /* dust and tracers: gas velocity */
+} pl_fields;
+
+typedef struct {
+    double *rho;            /* charge density (charged) or mass density (dust) */
+    double *J[3];           /* current density, charged only */
+    double *F[3];           /* force density m w du/dt, charged and dust */
+    double *eng;            /* energy-change density, charged only */
+} pl_moments;               /* NULL channels are skipped; tracers deposit nothing */
+
+typedef struct {
+    int box;                /* index into pl_init_desc.boxes */
+    int species;            /* index into pl_init_desc.species */
+    pl_particles p;
+    pl_fields f;
+    pl_moments m;
+} pl_item;
+
+/*
+ * pl_part_init: validate the description, allocate every piece of scratch the
+ * library will ever use (sort buffers for max_np particles, item tables for
+ * max_items, work counters, latched-error flags, pinned staging) and create
+ * the context.  Reads tune_cache when given.  On error *out is NULL.
+ */
+pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d);
+
+/*
+ * pl_part_gather_push: advance every particle of items[0..nitems) by one step
+ * of length dt (finite, non-zero): gather at x^n, push, new position x^{n+1}
+ * (periodic wrap).  Kinds, fields and channels are described above.
+ *   PL_FUSE_DEPOSIT  deposit the items' non-NULL moment channels at x^{n+1}
+ *                    in the same pass (added to the grids' contents);
+ *   PL_ZERO_FIRST    zero those channels first;
+ *   PL_SUMS          accumulate per-item particle-side sums (pl_part_sums);
+ *   PL_GRAPH         record the launches as a hipGraph keyed by the call's
+ *                    arguments and replay it on later identical calls
+ *                    (the stream must not be the null stream).
+ * All items go to one persistent launch per kernel stage.  Items must not
+ * share particle arrays; items sharing a moment grid add into it.
+ */
+pl_status pl_part_gather_push(pl_ctx *ctx, pl_item *items, int nitems, double dt, uint32_t flags);
+
+/*
+ * pl_part_deposit: deposit the current state of every item (no push): rho and
+ * J from the particles, F from p.fp (required when m.F is set), eng is not
+ * available here (must be NULL).  PL_ZERO_FIRST zeroes the channels first.
+ */
+pl_status pl_part_deposit(pl_ctx *ctx, const pl_item *items, int nitems, uint32_t flags);
+
+/*
+ * pl_part_sort: stable sort of each item's particles by cell-tile key (the
+ * context's key_mode and the box's tile), moving every SoA array (cell, x, u,
+ * w, id) from set cur into set 1-cur, writing p.tile_start, and flipping
+ * items[i].p.cur.  Equal keys keep their order (bit-identical to a stable
+ * sort).  Requires the 1-cur set for every non-NULL array of set cur.
+ */
+pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems);
+
+/*
+ * pl_part_pack: write item->p's current set from float64 device arrays
+ * x[3] (grid coordinates, wrapped into the box) and u[3]; for PL_F32_OFFSET
+ * this splits each coordinate into the packed cell and the float32 offset
+ * (an offset that rounds to +1/2 moves to the next cell at -1/2).
+ * pl_part_unpack writes the current state back as float64 grid coordinates
+ * and velocities.  x[2] may be NULL in 2D.
+ */
+pl_status pl_part_pack(pl_ctx *ctx, const pl_item *item, const double *x[3], const double *u[3]);
+pl_status pl_part_unpack(pl_ctx *ctx, const pl_item *item, double *x[3], double *u[3]);
+
+/*
+ * pl_part_sums: synchronous.  For each item writes 16 doubles to host array
+ * out: [0..8) grid sums of rho, J[3], F[3], eng times dV (0 for NULL
+ * channels), [8..16) the matching particle-side sums accumulated by the last
+ * gather_push called with PL_SUMS (sum q w (dust: m w), sum q w v, sum m w
+ * du/dt, sum m w c^2 dgamma/dt).  Conservation means the halves agree.
+ */
+pl_status pl_part_sums(pl_ctx *ctx, const pl_item *items, int nitems, double *out);
+
+/* Wait for the context's stream; return and clear latched device errors. */
+pl_status pl_part_sync(pl_ctx *ctx);
+
+/* Change the stream later work is queued on (drops recorded graphs). */
+pl_status pl_part_set_stream(pl_ctx *ctx, void *stream);
+
+/* Number of kernel launches and graph replays queued so far (diagnostics). */
+pl_status pl_part_stats(pl_ctx *ctx, int64_t out[4]);
+
+/* Free the context and its scratch (synchronises first).  NULL is a no-op. */
+void pl_part_finalize(pl_ctx *ctx);
+
+/* Static text for a status code. */
+const char *pl_status_string(pl_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PL_H */

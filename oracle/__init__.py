@@ -84,6 +84,8 @@ def lib():
                                               C.POINTER(C.c_uint32)]
         L.orc_split_position.restype = None
         L.orc_split_position.argtypes = [C.POINTER(_Box), _P, C.POINTER(C.c_long), C.POINTER(C.c_float)]
+        L.orc_num_threads.restype = C.c_int
+        L.orc_num_threads.argtypes = []
         L.orc_stable_sort_perm.restype = None
         L.orc_stable_sort_perm.argtypes = [C.c_long, C.POINTER(C.c_uint32), C.POINTER(C.c_long)]
         _LIB = L
@@ -222,6 +224,10 @@ def split_positions(ndim, n, x):
         cells[:, p] = cc[:]
         offs[:, p] = oo[:]
     return cells, offs
+
+
+def num_threads():
+    return lib().orc_num_threads()
 
 
 def stable_sort_perm(keys):

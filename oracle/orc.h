@@ -74,6 +74,9 @@ void orc_keys_from_positions(const orc_box *b, const int tile[3], int key_mode, 
  * the cell centre in [-1/2, 1/2), per dimension (the compact position form). */
 void orc_split_position(const orc_box *b, const double x[3], long cell[3], float off[3]);
 
+/* Threads the particle loop uses (OpenMP), for reporting timings. */
+int orc_num_threads(void);
+
 /* Stable sort: perm[r] = index of the particle that lands at rank r. */
 void orc_stable_sort_perm(long np, const uint32_t *key, long *perm);
 

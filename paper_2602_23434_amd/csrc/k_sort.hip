@@ -1,0 +1,273 @@
+// Stable cell-tile sort for gfx950.
+//
+// key(p) = tile of the particle's cell (or tile * cells_per_tile + cell in
+// tile).  The permutation is the stable one (ties keep their order), built by
+// least-significant-digit radix sort on (key, source index) pairs with 8-bit
+// digits: per pass a digit histogram per block, an exclusive scan in
+// digit-major order, and a scatter in which every wave ranks its 64 elements
+// by digit with ballots (so equal digits keep their order) and the block's
+// waves take consecutive sub-ranges.  The final index list moves every SoA
+// array into the alternate buffer set, and a boundary pass writes the
+// first-particle offset of every tile.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "pl_device.h"
+
+namespace pl {
+
+constexpr int kSortWaves = 8;
+constexpr int kSortThreads = kSortWaves * 64;
+constexpr int kPerWave = 1024;                       // elements per wave per block
+constexpr int kPerBlock = kSortWaves * kPerWave;     // elements per block
+constexpr int kScanBlocks = 512;
+
+__global__ void k_keys(SortArgs a, uint32_t *keys)
+{
+    const int tx = a.tile[0], ty = a.tile[1], tz = a.tile[2];
+    const int ntx = a.n[0] / tx, nty = a.n[1] / ty;
+    const int per_tile = tx * ty * tz;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < a.np; p += gridDim.x * blockDim.x) {
+        int c[3] = {0, 0, 0};
+        if (a.prec == PL_F32_OFFSET) {
+            unpack_cell(a.cell[p], c[0], c[1], c[2]);
+            for (int d = 0; d < 3; ++d)
+                if (c[d] >= a.n[d]) c[d] %= a.n[d];
+        } else {
+            for (int d = 0; d < a.ndim; ++d) {
+                double v = a.x[d][p];
+                double nn = (double)a.n[d];
+                if (!(v >= 0.0 && v < nn)) {
+                    if (!isfinite(v)) v = 0.0;
+                    v = v - nn * floor(v / nn);
+                    if (v >= nn || v < 0.0) v = 0.0;
+                }
+                c[d] = (int)floor(v);
+            }
+        }
+        int t = c[0] / tx + ntx * (c[1] / ty + nty * (c[2] / tz));
+        uint32_t key = (uint32_t)t;
+        if (a.key_mode == PL_KEY_TILE_CELL) {
+            int loc = c[0] % tx + tx * (c[1] % ty + ty * (c[2] % tz));
+            key = (uint32_t)t * (uint32_t)per_tile + (uint32_t)loc;
+        }
+        keys[p] = key;
+    }
+}
+
+// Per-block digit histogram, stored digit-major: hist[d * nblocks + b].
+__global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t *keys, int np, int shift, int nblocks,
+                                                       uint32_t *hist)
+{
+    __shared__ uint32_t h[256];
+    for (int d = threadIdx.x; d < 256; d += blockDim.x) h[d] = 0;
+    __syncthreads();
+    int beg = blockIdx.x * kPerBlock;
+    int end = min(np, beg + kPerBlock);
+    for (int e = beg + threadIdx.x; e < end; e += blockDim.x)
+        atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+    __syncthreads();
+    for (int d = threadIdx.x; d < 256; d += blockDim.x) hist[(size_t)d * nblocks + blockIdx.x] = h[d];
+}
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total)
+{
+    // sh: blockDim.x/64 entries
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    int nw = blockDim.x >> 6;
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < nw; ++k) {
+            uint32_t t = sh[k];
+            sh[k] = run;
+            run += t;
+        }
+        sh[nw] = run;
+    }
+    __syncthreads();
+    uint32_t r = x - v + sh[wv];
+    total = sh[nw];
+    __syncthreads();
+    return r;
+}
+
+// Three-kernel exclusive scan of hist[0..m): segment sums, scan of the sums,
+// segment scan with offsets.
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *in, long m, long seg, uint32_t *part)
+{
+    long beg = blockIdx.x * seg, end = min(m, beg + seg);
+    uint32_t s = 0;
+    for (long i = beg + threadIdx.x; i < end; i += blockDim.x) s += in[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    __shared__ uint32_t w[4];
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = w[0] + w[1] + w[2] + w[3];
+}
+
+__global__ __launch_bounds__(kScanBlocks) void k_scan_parts(uint32_t *part, int nparts)
+{
+    __shared__ uint32_t sh[kScanBlocks / 64 + 1];
+    uint32_t v = threadIdx.x < nparts ? part[threadIdx.x] : 0u;
+    uint32_t total;
+    uint32_t r = block_exclusive_scan(v, sh, total);
+    if (threadIdx.x < nparts) part[threadIdx.x] = r;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *in, long m, long seg, const uint32_t *part,
+                                                    uint32_t *out)
+{
+    __shared__ uint32_t sh[256 / 64 + 1];
+    long beg = blockIdx.x * seg, end = min(m, beg + seg);
+    uint32_t run = part[blockIdx.x];
+    for (long base = beg; base < end; base += blockDim.x) {
+        long i = base + threadIdx.x;
+        uint32_t v = i < end ? in[i] : 0u;
+        uint32_t total;
+        uint32_t r = block_exclusive_scan(v, sh, total);
+        if (i < end) out[i] = run + r;
+        run += total;
+    }
+}
+
+// Stable scatter of one radix pass.  idx_in == nullptr means identity
+// (first pass).
+__global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t *keys_in, const uint32_t *idx_in,
+                                                          uint32_t *keys_out, uint32_t *idx_out, int np,
+                                                          int shift, int nblocks, const uint32_t *offs)
+{
+    __shared__ uint32_t wc[kSortWaves][256];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int e = threadIdx.x; e < kSortWaves * 256; e += blockDim.x) (&wc[0][0])[e] = 0;
+    __syncthreads();
+    const int bbeg = blockIdx.x * kPerBlock;
+    const int wbeg = bbeg + wv * kPerWave;
+    const int wend = min(np, wbeg + kPerWave);
+    for (int e = wbeg + lane; e < wend; e += 64) atomicAdd(&wc[wv][(keys_in[e] >> shift) & 255u], 1u);
+    __syncthreads();
+    for (int d = threadIdx.x; d < 256; d += blockDim.x) {
+        uint32_t run = offs[(size_t)d * nblocks + blockIdx.x];
+        for (int w = 0; w < kSortWaves; ++w) {
+            uint32_t t = wc[w][d];
+            wc[w][d] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int base = wbeg; base < wend; base += 64) {
+        int e = base + lane;
+        bool valid = e < wend;
+        uint32_t k = valid ? keys_in[e] : 0u;
+        uint32_t id = valid ? (idx_in ? idx_in[e] : (uint32_t)e) : 0u;
+        uint32_t d = (k >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t m = __ballot(valid && ((d >> b) & 1u));
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        if (valid) {
+            uint32_t rank = (uint32_t)__popcll(peers & lt);
+            uint32_t dst = wc[wv][d] + rank;
+            keys_out[dst] = k;
+            idx_out[dst] = id;
+        }
+        // make every lane's read of wc[wv][d] happen before the update
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        if (valid) {
+            // highest lane of each peer group advances its digit's cursor
+            uint64_t higher = peers & ~(lt | (1ull << lane));
+            if (higher == 0) wc[wv][d] += (uint32_t)__popcll(peers);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+template <int ES>
+__global__ void k_permute(const uint32_t *perm, int np, const void *src, void *dst)
+{
+    using T = typename std::conditional<ES == 8, unsigned long long, uint32_t>::type;
+    const T *s = (const T *)src;
+    T *d = (T *)dst;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np; r += gridDim.x * blockDim.x) d[r] = s[perm[r]];
+}
+
+__global__ void k_tile_start(const uint32_t *keys, int np, int per_tile, int ntiles, int32_t *ts)
+{
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np; r += gridDim.x * blockDim.x) {
+        int t = (int)(keys[r] / (uint32_t)per_tile);
+        int prev = r > 0 ? (int)(keys[r - 1] / (uint32_t)per_tile) : -1;
+        for (int q = prev + 1; q <= t; ++q) ts[q] = r;
+        if (r == np - 1)
+            for (int q = t + 1; q <= ntiles; ++q) ts[q] = np;
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int n, int v)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_sort(Ctx *c, const SortArgs &a)
+{
+    hipStream_t s = c->stream;
+    if (a.np == 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(std::max(1, (a.ntiles + 256) / 256)), dim3(256), 0, s, a.tile_start,
+                           a.ntiles + 1, 0);
+        c->stats[0]++;
+        return hipGetLastError();
+    }
+    const int per_tile = a.key_mode == PL_KEY_TILE_CELL ? a.tile[0] * a.tile[1] * a.tile[2] : 1;
+    const uint64_t maxkey = (uint64_t)a.ntiles * per_tile - 1;
+    int bits = 1;
+    while (bits < 32 && (maxkey >> bits) != 0) ++bits;
+    const int npass = (bits + 7) / 8;
+    const int grid_e = std::min((a.np + 255) / 256, 16 * c->num_cu);
+
+    hipLaunchKernelGGL(k_keys, dim3(grid_e), dim3(256), 0, s, a, c->keys[0]);
+    c->stats[0]++;
+    const int nblocks = (a.np + kPerBlock - 1) / kPerBlock;
+    const long m = 256L * nblocks;
+    const long seg = (m + kScanBlocks - 1) / kScanBlocks;
+    const int nparts = (int)((m + seg - 1) / seg);
+    uint32_t *part = c->hist_scan + m;
+    int src = 0;
+    for (int pass = 0; pass < npass; ++pass) {
+        int shift = 8 * pass;
+        hipLaunchKernelGGL(k_hist, dim3(nblocks), dim3(kSortThreads), 0, s, c->keys[src], a.np, shift, nblocks,
+                           c->hist);
+        hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(256), 0, s, c->hist, m, seg, part);
+        hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanBlocks), 0, s, part, nparts);
+        hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(256), 0, s, c->hist, m, seg, part, c->hist_scan);
+        hipLaunchKernelGGL(k_scatter, dim3(nblocks), dim3(kSortThreads), 0, s, c->keys[src],
+                           pass == 0 ? (const uint32_t *)nullptr : c->idx[src], c->keys[1 - src], c->idx[1 - src],
+                           a.np, shift, nblocks, c->hist_scan);
+        c->stats[0] += 5;
+        src = 1 - src;
+    }
+    const uint32_t *perm = c->idx[src];
+    for (int k = 0; k < a.narrays; ++k) {
+        if (a.esize[k] == 8)
+            hipLaunchKernelGGL(k_permute<8>, dim3(grid_e), dim3(256), 0, s, perm, a.np, a.src[k], a.dst[k]);
+        else
+            hipLaunchKernelGGL(k_permute<4>, dim3(grid_e), dim3(256), 0, s, perm, a.np, a.src[k], a.dst[k]);
+        c->stats[0]++;
+    }
+    hipLaunchKernelGGL(k_tile_start, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, per_tile, a.ntiles,
+                       a.tile_start);
+    c->stats[0]++;
+    return hipGetLastError();
+}
+
+}  // namespace pl

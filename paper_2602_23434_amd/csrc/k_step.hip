@@ -1,0 +1,751 @@
+// Gather -> push -> deposit kernels for gfx950.
+//
+// One templated body serves both algorithms:
+//  * PLAIN: one thread per particle; fields are read from HBM/L2 at the 27
+//    (TSC) stencil cells and every deposit is a float64 global atomic.
+//  * TILED: one work unit per (item, cell tile).  The block stages the tile's
+//    fields plus a one-cell halo into LDS (converted to the arithmetic type),
+//    processes the particles the last cell-tile sort assigned to the tile,
+//    accumulates their deposits in an LDS tile, and flushes it with one
+//    float64 global atomic per touched cell and channel.  A particle whose
+//    stencil leaves the LDS tile (it drifted since the sort) takes the plain
+//    route for that gather or deposit, so results never depend on the sort.
+// Work units of all items of a call are claimed from one atomic counter by a
+// persistent grid sized to the chip's resident capacity; items are ordered
+// largest first on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+
+#include "pl_device.h"
+
+namespace pl {
+
+enum StepFlag : unsigned {
+    SF_PUSH = 1u,       // advance particles (else: deposit the current state)
+    SF_DEPOSIT = 2u,    // deposit moments
+    SF_SUMS = 4u,       // particle-side conservation sums
+};
+
+template <int DIM> struct Stencil {
+    static constexpr int SY = DIM >= 2 ? 3 : 1;
+    static constexpr int SZ = DIM >= 3 ? 3 : 1;
+};
+
+// Work-unit claim shared by every persistent kernel: returns a wave-uniform
+// unit index, or -1 when the work is exhausted.
+__device__ __forceinline__ int claim_unit(unsigned *counter, int total, int *s_slot)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) *s_slot = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    int g = __builtin_amdgcn_readfirstlane(*s_slot);
+    return g < total ? g : -1;
+}
+
+// The last block to finish resets the counter pair for the next launch.
+__device__ __forceinline__ void release_counter(unsigned *counter)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned done = atomicAdd(counter + 1, 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(counter, 0u);
+            atomicExch(counter + 1, 0u);
+        }
+    }
+}
+
+__device__ __forceinline__ int find_item(const ItemDesc *items, int nitems, int g)
+{
+    int it = 0;
+    while (it + 1 < nitems && items[it + 1].unit_begin <= g) ++it;
+    return it;
+}
+
+template <typename R>
+__device__ __forceinline__ R wave_sum(R v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Per-unit constants: read once from the item table into registers when a
+// block claims a unit, so the particle loop never goes back to memory (or
+// waits on the scalar cache) for them.
+template <int PREC> struct UnitC {
+    using R = typename RealOf<PREC>::T;
+    int n[3];
+    int np, kind;
+    R h, inv_c2, c2, q, m, wdef, inv_dt, decay, one_m_decay;
+    R dtdx[3];
+    double inv_dv;
+    uint32_t *cell;
+    R *x[3];
+    R *u[3];
+    const R *w;
+    R *fp[3];
+    const double *gf[6];
+    double *M[kMaxCh];
+    int soff[kMaxCh];      // offset of each active channel in the LDS deposit tile, -1 if inactive
+};
+
+template <int PREC>
+__device__ __forceinline__ void load_unit(const ItemDesc &I, UnitC<PREC> &U, int L)
+{
+    using R = typename RealOf<PREC>::T;
+    for (int a = 0; a < 3; ++a) {
+        U.n[a] = I.n[a];
+        U.dtdx[a] = (R)I.dtdx[a];
+        U.x[a] = (R *)I.x[a];
+        U.u[a] = (R *)I.u[a];
+        U.fp[a] = (R *)I.fp[a];
+    }
+    U.np = I.np;
+    U.kind = I.kind;
+    U.h = (R)I.h;
+    U.inv_c2 = (R)I.inv_c2;
+    U.c2 = (R)I.c2;
+    U.q = (R)I.q;
+    U.m = (R)I.m;
+    U.wdef = (R)I.wdef;
+    U.inv_dt = (R)I.inv_dt;
+    U.decay = (R)I.decay;
+    U.one_m_decay = (R)I.one_m_decay;
+    U.inv_dv = I.inv_dv;
+    U.cell = I.cell;
+    U.w = (const R *)I.w;
+    if (I.kind == PL_LORENTZ) {
+        for (int a = 0; a < 3; ++a) {
+            U.gf[a] = I.E[a];
+            U.gf[3 + a] = I.B[a];
+        }
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            U.gf[a] = I.vg[a];
+            U.gf[3 + a] = nullptr;
+        }
+    }
+    for (int ch = 0; ch < kMaxCh; ++ch) {
+        U.M[ch] = I.M[ch];
+        U.soff[ch] = I.slot[ch] >= 0 ? I.slot[ch] * L : -1;
+    }
+}
+
+// Tile geometry of one work unit in the LDS (one-cell halo on every side).
+struct TileGeo {
+    int lo[3];
+    int T[3];
+    int Lx, LxLy, L;
+};
+
+template <int DIM>
+__device__ __forceinline__ bool in_tile(const TileGeo &tg, const int c[3], int &base)
+{
+    int l0 = c[0] - tg.lo[0], l1 = DIM >= 2 ? c[1] - tg.lo[1] : 0, l2 = DIM >= 3 ? c[2] - tg.lo[2] : 0;
+    bool ok = (unsigned)l0 < (unsigned)tg.T[0];
+    if (DIM >= 2) ok = ok && (unsigned)l1 < (unsigned)tg.T[1];
+    if (DIM >= 3) ok = ok && (unsigned)l2 < (unsigned)tg.T[2];
+    // LDS cell index of stencil offset (-1,-1,-1) relative to the particle's cell
+    base = l0 + (DIM >= 2 ? l1 * tg.Lx : 0) + (DIM >= 3 ? l2 * tg.LxLy : 0);
+    return ok;
+}
+
+// Interpolate NC field components at a particle in cell c with 1D weights
+// wx, wy, wz: from the LDS tile (component-major, L cells per component) when
+// the stencil lies inside it, otherwise from the float64 grids in HBM.  Both
+// routes add the same terms in the same order with explicit fused
+// multiply-adds, so the result does not depend on the route.
+template <int PREC, int DIM, int NC>
+__device__ __forceinline__ void gather(const UnitC<PREC> &U, const typename RealOf<PREC>::T *lds_f, int L, bool use_lds,
+                                       int base, int Lx, int LxLy, const int c[3],
+                                       const typename RealOf<PREC>::T wx[3], const typename RealOf<PREC>::T wy[3],
+                                       const typename RealOf<PREC>::T wz[3], typename RealOf<PREC>::T out[NC])
+{
+    using R = typename RealOf<PREC>::T;
+    constexpr int SY = Stencil<DIM>::SY, SZ = Stencil<DIM>::SZ;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) out[q] = R(0);
+    if (use_lds) {
+#pragma unroll
+        for (int k = 0; k < SZ; ++k)
+#pragma unroll
+            for (int j = 0; j < SY; ++j) {
+                R wyz = wz[k] * wy[j];
+                int row = base + k * LxLy + j * Lx;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    R w = wyz * wx[i];
+#pragma unroll
+                    for (int q = 0; q < NC; ++q) out[q] = fma(w, lds_f[q * L + row + i], out[q]);
+                }
+            }
+    } else {
+        const int *n = U.n;
+        int ix[3] = {wrap_cell(c[0] - 1, n[0]), c[0], wrap_cell(c[0] + 1, n[0])};
+        int iy[3] = {wrap_cell(c[1] - 1, n[1]), c[1], wrap_cell(c[1] + 1, n[1])};
+        int iz[3] = {DIM >= 3 ? wrap_cell(c[2] - 1, n[2]) : c[2], c[2], DIM >= 3 ? wrap_cell(c[2] + 1, n[2]) : c[2]};
+#pragma unroll
+        for (int k = 0; k < SZ; ++k)
+#pragma unroll
+            for (int j = 0; j < SY; ++j) {
+                R wyz = wz[k] * wy[j];
+                long row = (long)n[0] * (iy[j] + (long)n[1] * iz[k]);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    R w = wyz * wx[i];
+                    long g = row + ix[i];
+#pragma unroll
+                    for (int q = 0; q < NC; ++q) out[q] = fma(w, (R)U.gf[q][g], out[q]);
+                }
+            }
+    }
+}
+
+// Deposit mu[ch] * W into the float64 LDS tile (or straight into the grids
+// when the stencil leaves the tile).  LDS float64 adds are used because on
+// gfx950 they run about ten times faster than float32 LDS atomic adds.
+template <int PREC, int DIM>
+__device__ __forceinline__ void deposit(const UnitC<PREC> &U, double *lds_d, bool use_lds, int base, int Lx,
+                                        int LxLy, const int c[3], const typename RealOf<PREC>::T wx[3],
+                                        const typename RealOf<PREC>::T wy[3], const typename RealOf<PREC>::T wz[3],
+                                        const double mu[kMaxCh])
+{
+    using R = typename RealOf<PREC>::T;
+    constexpr int SY = Stencil<DIM>::SY, SZ = Stencil<DIM>::SZ;
+    if (use_lds) {
+#pragma unroll
+        for (int k = 0; k < SZ; ++k)
+#pragma unroll
+            for (int j = 0; j < SY; ++j) {
+                R wyz = wz[k] * wy[j];
+                int row = base + k * LxLy + j * Lx;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    double w = (double)(wyz * wx[i]);
+#pragma unroll
+                    for (int ch = 0; ch < kMaxCh; ++ch) {
+                        int so = U.soff[ch];
+                        if (so >= 0)
+                            __hip_atomic_fetch_add(lds_d + so + row + i, w * mu[ch], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+            }
+    } else {
+        const int *n = U.n;
+        int ix[3] = {wrap_cell(c[0] - 1, n[0]), c[0], wrap_cell(c[0] + 1, n[0])};
+        int iy[3] = {wrap_cell(c[1] - 1, n[1]), c[1], wrap_cell(c[1] + 1, n[1])};
+        int iz[3] = {DIM >= 3 ? wrap_cell(c[2] - 1, n[2]) : c[2], c[2], DIM >= 3 ? wrap_cell(c[2] + 1, n[2]) : c[2]};
+#pragma unroll
+        for (int k = 0; k < SZ; ++k)
+#pragma unroll
+            for (int j = 0; j < SY; ++j) {
+                R wyz = wz[k] * wy[j];
+                long row = (long)n[0] * (iy[j] + (long)n[1] * iz[k]);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    double w = (double)(wyz * wx[i]) * U.inv_dv;
+                    long g = row + ix[i];
+#pragma unroll
+                    for (int ch = 0; ch < kMaxCh; ++ch)
+                        if (U.soff[ch] >= 0) global_add(U.M[ch] + g, w * mu[ch]);
+                }
+            }
+    }
+}
+
+template <int PREC, int SHAPE, int DIM>
+__device__ __forceinline__ void stencil_weights(const typename RealOf<PREC>::T d[3], typename RealOf<PREC>::T wx[3],
+                                                typename RealOf<PREC>::T wy[3], typename RealOf<PREC>::T wz[3])
+{
+    using R = typename RealOf<PREC>::T;
+    weights3<SHAPE>(d[0], wx);
+    weights3<SHAPE>(d[1], wy);
+    if (DIM >= 3) {
+        weights3<SHAPE>(d[2], wz);
+    } else {
+        wz[0] = R(1); wz[1] = R(0); wz[2] = R(0);
+    }
+}
+
+// LDS bytes of one work unit: field tile (when pushing) + float64 deposit tile
+// + a 16-byte tail holding the claimed unit index.
+__host__ __device__ inline size_t step_lds_bytes(int prec, int kind, int L, bool push, int nslot)
+{
+    size_t rs = prec == PL_F64 ? 8 : 4;
+    int nf = kind == PL_LORENTZ ? 6 : 3;
+    size_t f = push ? (size_t)L * nf * rs : 0;
+    f = (f + 15) & ~(size_t)15;
+    return f + (size_t)L * nslot * 8 + 16;
+}
+
+template <int PREC, int SHAPE, int DIM, bool TILED>
+__global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items, int nitems, int total_units,
+                                               unsigned *counter, int *errflags, unsigned flags, int lds_bytes)
+{
+    using R = typename RealOf<PREC>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int *s_unit = reinterpret_cast<int *>(smem_raw + lds_bytes - 16);
+
+    const bool do_push = flags & SF_PUSH;
+    const bool do_dep = flags & SF_DEPOSIT;
+    const bool do_sums = flags & SF_SUMS;
+    int err = 0;
+
+    for (;;) {
+        int g = claim_unit(counter, total_units, s_unit);
+        if (g < 0) break;
+        const int iti = find_item(items, nitems, g);
+        const ItemDesc &I = items[iti];
+        const int unit = g - I.unit_begin;
+        TileGeo tg;
+        int pbeg, pend;
+        if (TILED) {
+            int t = unit;
+            int tx = t % I.ntile[0];
+            int ty = (t / I.ntile[0]) % I.ntile[1];
+            int tz = t / (I.ntile[0] * I.ntile[1]);
+            tg.T[0] = I.tile[0];
+            tg.T[1] = I.tile[1];
+            tg.T[2] = I.tile[2];
+            tg.lo[0] = tx * tg.T[0];
+            tg.lo[1] = ty * tg.T[1];
+            tg.lo[2] = tz * tg.T[2];
+            tg.Lx = tg.T[0] + 2;
+            tg.LxLy = tg.Lx * (tg.T[1] + 2);
+            tg.L = tg.LxLy * (DIM >= 3 ? tg.T[2] + 2 : 1);
+            int a = I.tile_start[t], b = I.tile_start[t + 1];
+            pbeg = min(max(a, 0), I.np);
+            pend = min(max(b, pbeg), I.np);
+        } else {
+            tg.Lx = tg.LxLy = tg.L = 0;
+            tg.lo[0] = tg.lo[1] = tg.lo[2] = 0;
+            tg.T[0] = tg.T[1] = tg.T[2] = 0;
+            pbeg = unit * I.chunk;
+            pend = min(I.np, pbeg + I.chunk);
+        }
+        if (pbeg >= pend) continue;        // uniform: the whole block skips an empty unit
+
+        UnitC<PREC> U;
+        load_unit<PREC>(I, U, tg.L);
+        const int kind = U.kind;
+        const bool dep_here = do_dep && kind != PL_TRACER && I.nslot > 0;
+        const int nslot = I.nslot;
+        const int nf = kind == PL_LORENTZ ? 6 : 3;
+        R *lds_f = reinterpret_cast<R *>(smem_raw);
+        size_t foff = do_push ? ((size_t)tg.L * nf * sizeof(R) + 15) & ~(size_t)15 : 0;
+        double *lds_d = reinterpret_cast<double *>(smem_raw + foff);
+
+        if (TILED) {
+            const int Ly = tg.T[1] + 2;
+            for (int e = threadIdx.x; e < tg.L; e += blockDim.x) {
+                int lx = e % tg.Lx;
+                int ly = (e / tg.Lx) % Ly;
+                int lz = e / tg.LxLy;
+                int gx = wrap_cell(tg.lo[0] + lx - 1, U.n[0]);
+                int gy = wrap_cell(tg.lo[1] + ly - 1, U.n[1]);
+                int gz = DIM >= 3 ? wrap_cell(tg.lo[2] + lz - 1, U.n[2]) : 0;
+                long gc = gx + (long)U.n[0] * (gy + (long)U.n[1] * gz);
+                if (do_push)
+                    for (int q = 0; q < nf; ++q) lds_f[q * tg.L + e] = (R)U.gf[q][gc];
+                if (dep_here)
+                    for (int s = 0; s < nslot; ++s) lds_d[s * tg.L + e] = 0.0;
+            }
+            __syncthreads();
+        }
+
+        double ps[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ps[k] = 0.0;
+
+        // Tiled: thread t takes the contiguous run [pbeg + t*run, +run) of the
+        // tile's particles.  With particles sorted by cell, the 64 lanes of a
+        // wave then sit in about 64 consecutive cells at every step of the
+        // run, so their LDS reads and adds fall in distinct banks.  Plain: one
+        // particle per thread, grid-strided.
+        const int run = TILED ? (pend - pbeg + (int)blockDim.x - 1) / (int)blockDim.x : 1;
+        const int pfirst = TILED ? pbeg + (int)threadIdx.x * run : pbeg + (int)threadIdx.x;
+        const int plast = TILED ? min(pend, pfirst + run) : pend;
+        const int pstep = TILED ? 1 : (int)blockDim.x;
+        for (int p = pfirst; p < plast; p += pstep) {
+            Pos<PREC, DIM> pos;
+            pos.load(U, p, err);
+            R u[3] = {U.u[0][p], U.u[1][p], U.u[2][p]};
+            R w = U.w ? U.w[p] : U.wdef;
+            double mu[kMaxCh];
+#pragma unroll
+            for (int ch = 0; ch < kMaxCh; ++ch) mu[ch] = 0.0;
+
+            if (do_push) {
+                R d0[3] = {(R)pos.d[0], (R)pos.d[1], (R)pos.d[2]};
+                R wx[3], wy[3], wz[3];
+                stencil_weights<PREC, SHAPE, DIM>(d0, wx, wy, wz);
+                int base = 0;
+                bool inl = TILED && in_tile<DIM>(tg, pos.c, base);
+                R v[3];
+                if (kind == PL_LORENTZ) {
+                    R EB[6];
+                    gather<PREC, DIM, 6>(U, lds_f, tg.L, inl, base, tg.Lx, tg.LxLy, pos.c, wx, wy, wz, EB);
+                    R du[3];
+                    R uo[3] = {u[0], u[1], u[2]};
+                    R u_old2 = fma(u[0], u[0], fma(u[1], u[1], u[2] * u[2]));
+                    boris<R>(u, EB, EB + 3, U.h, U.inv_c2, du);
+                    R u_new2 = fma(u[0], u[0], fma(u[1], u[1], u[2] * u[2]));
+                    R gn = sqrt(fma(u_new2, U.inv_c2, R(1)));
+                    R go = sqrt(fma(u_old2, U.inv_c2, R(1)));
+                    R ig = R(1) / gn;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) v[a] = u[a] * ig;
+                    R qw = U.q * w, mw = U.m * w;
+                    mu[0] = (double)qw;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        mu[1 + a] = (double)(qw * v[a]);
+                        mu[4 + a] = (double)(mw * du[a] * U.inv_dt);
+                    }
+                    if (PREC == PL_F64) {
+                        mu[7] = (double)(mw * U.c2 * (gn - go) * U.inv_dt);
+                    } else {
+                        // c^2 (gamma_new - gamma_old) without the cancellation:
+                        // (|u_new|^2 - |u_old|^2) / (gamma_new + gamma_old)
+                        R dd = fma(du[0], u[0] + uo[0], fma(du[1], u[1] + uo[1], du[2] * (u[2] + uo[2])));
+                        mu[7] = (double)(mw * dd / (gn + go) * U.inv_dt);
+                    }
+                    if (U.fp[0]) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) U.fp[a][p] = (R)mu[4 + a];
+                    }
+                } else if (kind == PL_DUST) {
+                    R vg[3];
+                    gather<PREC, DIM, 3>(U, lds_f, tg.L, inl, base, tg.Lx, tg.LxLy, pos.c, wx, wy, wz, vg);
+                    R du[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        du[a] = (vg[a] - u[a]) * U.one_m_decay;
+                        u[a] = vg[a] + (u[a] - vg[a]) * U.decay;
+                        v[a] = u[a];
+                    }
+                    R mw = U.m * w;
+                    mu[0] = (double)mw;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) mu[4 + a] = (double)(mw * du[a] * U.inv_dt);
+                    if (U.fp[0]) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) U.fp[a][p] = (R)mu[4 + a];
+                    }
+                } else {
+                    // tracer: Heun's two-stage Runge-Kutta on the frozen gas velocity
+                    R k1[3], k2[3];
+                    gather<PREC, DIM, 3>(U, lds_f, tg.L, inl, base, tg.Lx, tg.LxLy, pos.c, wx, wy, wz, k1);
+                    Pos<PREC, DIM> mid = pos;
+                    R d1[3] = {R(0), R(0), R(0)};
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) d1[a] = k1[a] * U.dtdx[a];
+                    mid.advance(d1, U, err);
+                    R dm[3] = {(R)mid.d[0], (R)mid.d[1], (R)mid.d[2]};
+                    stencil_weights<PREC, SHAPE, DIM>(dm, wx, wy, wz);
+                    int base2 = 0;
+                    bool inl2 = TILED && in_tile<DIM>(tg, mid.c, base2);
+                    gather<PREC, DIM, 3>(U, lds_f, tg.L, inl2, base2, tg.Lx, tg.LxLy, mid.c, wx, wy, wz, k2);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        u[a] = R(0.5) * (k1[a] + k2[a]);
+                        v[a] = u[a];
+                    }
+                }
+                R disp[3] = {R(0), R(0), R(0)};
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) disp[a] = v[a] * U.dtdx[a];
+                pos.advance(disp, U, err);
+                pos.store(U, p);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) U.u[a][p] = u[a];
+            } else {
+                // deposit of the current state
+                if (kind == PL_LORENTZ) {
+                    R g2 = sqrt(fma(fma(u[0], u[0], fma(u[1], u[1], u[2] * u[2])), U.inv_c2, R(1)));
+                    R qw = U.q * w;
+                    mu[0] = (double)qw;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) mu[1 + a] = (double)(qw * u[a] / g2);
+                } else {
+                    mu[0] = (double)(U.m * w);
+                }
+                if (U.fp[0]) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) mu[4 + a] = (double)U.fp[a][p];
+                }
+            }
+
+            if (do_sums) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) ps[k] += mu[k];
+            }
+
+            if (dep_here) {
+                R dn[3] = {(R)pos.d[0], (R)pos.d[1], (R)pos.d[2]};
+                R wx[3], wy[3], wz[3];
+                stencil_weights<PREC, SHAPE, DIM>(dn, wx, wy, wz);
+                int base = 0;
+                bool inl = TILED && in_tile<DIM>(tg, pos.c, base);
+                deposit<PREC, DIM>(U, lds_d, inl, base, tg.Lx, tg.LxLy, pos.c, wx, wy, wz, mu);
+            }
+        }
+
+        if (do_sums && kind != PL_TRACER) {
+            for (int k = 0; k < 8; ++k) {
+                double sw = wave_sum(ps[k]);
+                if ((threadIdx.x & 63) == 0 && sw != 0.0) global_add(I.psum + k, sw);
+            }
+        }
+
+        if (TILED && dep_here) {
+            __syncthreads();
+            const int Ly = tg.T[1] + 2;
+            for (int e = threadIdx.x; e < tg.L; e += blockDim.x) {
+                int lx = e % tg.Lx;
+                int ly = (e / tg.Lx) % Ly;
+                int lz = e / tg.LxLy;
+                int gx = wrap_cell(tg.lo[0] + lx - 1, U.n[0]);
+                int gy = wrap_cell(tg.lo[1] + ly - 1, U.n[1]);
+                int gz = DIM >= 3 ? wrap_cell(tg.lo[2] + lz - 1, U.n[2]) : 0;
+                long gc = gx + (long)U.n[0] * (gy + (long)U.n[1] * gz);
+#pragma unroll
+                for (int ch = 0; ch < kMaxCh; ++ch) {
+                    int so = U.soff[ch];
+                    if (so < 0) continue;
+                    double val = lds_d[so + e];
+                    if (val != 0.0) global_add(U.M[ch] + gc, val * U.inv_dv);
+                }
+            }
+        }
+    }
+
+    // latch device-side conditions
+    unsigned long long any = __ballot(err != 0);
+    if (any) {
+        int e = err;
+        for (int off = 32; off > 0; off >>= 1) e |= __shfl_xor(e, off, 64);
+        if ((threadIdx.x & 63) == 0) atomicOr(errflags, e);
+    }
+    release_counter(counter);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+using StepKernel = void (*)(const ItemDesc *, int, int, unsigned *, int *, unsigned, int);
+
+static StepKernel pick(int prec, int shape, int dim, bool tiled)
+{
+#define PL_PICK(P, S, D, T) \
+    if (prec == P && shape == S && dim == D && tiled == T) return k_step<P, S, D, T>;
+    PL_PICK(PL_F64, PL_TSC, 3, false) PL_PICK(PL_F64, PL_TSC, 3, true)
+    PL_PICK(PL_F64, PL_TSC, 2, false) PL_PICK(PL_F64, PL_TSC, 2, true)
+    PL_PICK(PL_F64, PL_CIC, 3, false) PL_PICK(PL_F64, PL_CIC, 3, true)
+    PL_PICK(PL_F64, PL_CIC, 2, false) PL_PICK(PL_F64, PL_CIC, 2, true)
+    PL_PICK(PL_F32_OFFSET, PL_TSC, 3, false) PL_PICK(PL_F32_OFFSET, PL_TSC, 3, true)
+    PL_PICK(PL_F32_OFFSET, PL_TSC, 2, false) PL_PICK(PL_F32_OFFSET, PL_TSC, 2, true)
+    PL_PICK(PL_F32_OFFSET, PL_CIC, 3, false) PL_PICK(PL_F32_OFFSET, PL_CIC, 3, true)
+    PL_PICK(PL_F32_OFFSET, PL_CIC, 2, false) PL_PICK(PL_F32_OFFSET, PL_CIC, 2, true)
+#undef PL_PICK
+    return nullptr;
+}
+
+static int resident_blocks(Ctx *c, StepKernel k, int block, size_t lds)
+{
+    static std::map<std::pair<const void *, std::pair<int, size_t>>, int> cache;
+    auto key = std::make_pair((const void *)k, std::make_pair(block, lds));
+    auto f = cache.find(key);
+    if (f != cache.end()) return f->second;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    int r = per_cu * c->num_cu;
+    cache[key] = r;
+    return r;
+}
+
+hipError_t launch_step(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc> &host, int nitems,
+                       int total_units, unsigned flags, bool deposit, bool push)
+{
+    if (total_units <= 0) return hipSuccess;
+    const bool tiled = c->d.algo == PL_ALGO_TILED;
+    StepKernel k = pick(c->d.prec, c->d.shape, c->d.ndim, tiled);
+    if (!k) return hipErrorInvalidValue;
+    unsigned sf = (push ? SF_PUSH : 0u) | (deposit ? SF_DEPOSIT : 0u) | ((flags & PL_SUMS) ? SF_SUMS : 0u);
+    size_t lds = 16;
+    if (tiled) {
+        for (const ItemDesc &it : host) {
+            int Lx = it.tile[0] + 2;
+            int Ly = it.tile[1] + 2;
+            int Lz = c->d.ndim >= 3 ? it.tile[2] + 2 : 1;
+            int L = Lx * Ly * Lz;
+            int ns = (deposit && it.kind != PL_TRACER) ? it.nslot : 0;
+            lds = std::max(lds, step_lds_bytes(c->d.prec, it.kind, L, push, ns));
+        }
+        if (lds > (size_t)c->lds_max) return hipErrorInvalidConfiguration;
+    }
+    int block = c->block;
+    int grid = std::min(total_units, resident_blocks(c, k, block, lds));
+    hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, c->stream, table, nitems, total_units, c->counters,
+                       c->errflags, sf, (int)lds);
+    c->stats[0]++;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Zeroing, sums, pack / unpack
+// ---------------------------------------------------------------------------
+
+__global__ void k_zero(double *p, long n)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+hipError_t launch_zero(Ctx *c, const std::vector<ItemDesc> &host)
+{
+    for (const ItemDesc &it : host) {
+        if (it.kind == PL_TRACER) continue;
+        long cells = (long)it.n[0] * it.n[1] * it.n[2];
+        int grid = (int)std::min<long>((cells + 255) / 256, 8L * c->num_cu);
+        for (int ch = 0; ch < kMaxCh; ++ch) {
+            if (it.slot[ch] < 0) continue;
+            hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, c->stream, it.M[ch], cells);
+            c->stats[0]++;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_sums(Ctx *c, double *sums, int n)
+{
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, c->stream, sums, (long)n);
+    c->stats[0]++;
+    return hipGetLastError();
+}
+
+__global__ void k_grid_sum(const double *p, long n, double scale, double *out)
+{
+    double s = 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) s += p[i];
+    s = wave_sum(s);
+    __shared__ double part[16];
+    int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) part[wv] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += part[k];
+        global_add(out, t * scale);
+    }
+}
+
+hipError_t launch_grid_sums(Ctx *c, const ItemDesc &it, double *out8)
+{
+    long cells = (long)it.n[0] * it.n[1] * it.n[2];
+    double dv = 1.0 / it.inv_dv;
+    int grid = (int)std::min<long>((cells + 255) / 256, 4L * c->num_cu);
+    for (int ch = 0; ch < kMaxCh; ++ch) {
+        if (!it.M[ch]) continue;
+        hipLaunchKernelGGL(k_grid_sum, dim3(grid), dim3(256), 0, c->stream, it.M[ch], cells, dv, out8 + ch);
+        c->stats[0]++;
+    }
+    return hipGetLastError();
+}
+
+template <int PREC>
+__global__ void k_pack(ItemDesc it, int ndim, const double *x0, const double *x1, const double *x2,
+                       const double *u0, const double *u1, const double *u2, int *errflags)
+{
+    const double *xs[3] = {x0, x1, x2};
+    const double *us[3] = {u0, u1, u2};
+    int err = 0;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < it.np; p += gridDim.x * blockDim.x) {
+        int c[3] = {0, 0, 0};
+        double xw[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(us[a][p])) err |= ERR_NONFINITE;
+        for (int a = 0; a < ndim; ++a) {
+            double v = xs[a][p];
+            double nn = (double)it.n[a];
+            if (!(v >= 0.0 && v < nn)) {
+                if (!isfinite(v)) { v = 0.0; err |= ERR_NONFINITE; }
+                v = v - nn * floor(v / nn);
+                if (v >= nn || v < 0.0) v = 0.0;
+            }
+            xw[a] = v;
+        }
+        if (PREC == PL_F64) {
+            for (int a = 0; a < ndim; ++a) ((double *)it.x[a])[p] = xw[a];
+            for (int a = 0; a < 3; ++a) ((double *)it.u[a])[p] = us[a][p];
+        } else {
+            for (int a = 0; a < ndim; ++a) {
+                double f = floor(xw[a]);
+                int ci = (int)f;
+                float o = (float)(xw[a] - f - 0.5);
+                if (o >= 0.5f) {
+                    o = -0.5f;
+                    ci = ci + 1 == it.n[a] ? 0 : ci + 1;
+                }
+                c[a] = ci;
+                ((float *)it.x[a])[p] = o;
+            }
+            it.cell[p] = pack_cell(c[0], c[1], c[2]);
+            for (int a = 0; a < 3; ++a) ((float *)it.u[a])[p] = (float)us[a][p];
+        }
+    }
+    if (err) atomicOr(errflags, err);
+}
+
+template <int PREC>
+__global__ void k_unpack(ItemDesc it, int ndim, double *x0, double *x1, double *x2, double *u0, double *u1,
+                         double *u2)
+{
+    double *xs[3] = {x0, x1, x2};
+    double *us[3] = {u0, u1, u2};
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < it.np; p += gridDim.x * blockDim.x) {
+        if (PREC == PL_F64) {
+            for (int a = 0; a < ndim; ++a) xs[a][p] = ((const double *)it.x[a])[p];
+            for (int a = 0; a < 3; ++a) us[a][p] = ((const double *)it.u[a])[p];
+        } else {
+            int c[3];
+            unpack_cell(it.cell[p], c[0], c[1], c[2]);
+            for (int a = 0; a < ndim; ++a) xs[a][p] = (double)c[a] + 0.5 + (double)((const float *)it.x[a])[p];
+            for (int a = 0; a < 3; ++a) us[a][p] = (double)((const float *)it.u[a])[p];
+        }
+    }
+}
+
+hipError_t launch_pack(Ctx *c, const ItemDesc &it, int prec, int ndim, const double *x[3], const double *u[3])
+{
+    if (it.np == 0) return hipSuccess;
+    int grid = std::min((it.np + 255) / 256, 16 * c->num_cu);
+    if (prec == PL_F64)
+        hipLaunchKernelGGL(k_pack<PL_F64>, dim3(grid), dim3(256), 0, c->stream, it, ndim, x[0], x[1], x[2], u[0],
+                           u[1], u[2], c->errflags);
+    else
+        hipLaunchKernelGGL(k_pack<PL_F32_OFFSET>, dim3(grid), dim3(256), 0, c->stream, it, ndim, x[0], x[1], x[2],
+                           u[0], u[1], u[2], c->errflags);
+    c->stats[0]++;
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(Ctx *c, const ItemDesc &it, int prec, int ndim, double *x[3], double *u[3])
+{
+    if (it.np == 0) return hipSuccess;
+    int grid = std::min((it.np + 255) / 256, 16 * c->num_cu);
+    if (prec == PL_F64)
+        hipLaunchKernelGGL(k_unpack<PL_F64>, dim3(grid), dim3(256), 0, c->stream, it, ndim, x[0], x[1], x[2], u[0],
+                           u[1], u[2]);
+    else
+        hipLaunchKernelGGL(k_unpack<PL_F32_OFFSET>, dim3(grid), dim3(256), 0, c->stream, it, ndim, x[0], x[1], x[2],
+                           u[0], u[1], u[2]);
+    c->stats[0]++;
+    return hipGetLastError();
+}
+
+}  // namespace pl

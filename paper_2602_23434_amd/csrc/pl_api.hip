@@ -1,0 +1,617 @@
+// C ABI of libpl.so: argument validation, context and scratch, item tables,
+// hipGraph record/replay, and dispatch to the kernels.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "pl_internal.h"
+
+using namespace pl;
+
+#define PL_TRY_HIP(expr)                        \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess) return PL_EHIP;   \
+    } while (0)
+
+namespace {
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+pl_status validate_desc(const pl_init_desc *d)
+{
+    if (!d) return PL_EINVAL;
+    if (d->ndim != 2 && d->ndim != 3) return PL_EINVAL;
+    if (d->prec != PL_F64 && d->prec != PL_F32_OFFSET) return PL_EINVAL;
+    if (d->shape != PL_CIC && d->shape != PL_TSC) return PL_EINVAL;
+    if (d->algo != PL_ALGO_PLAIN && d->algo != PL_ALGO_TILED) return PL_EINVAL;
+    if (d->key_mode != PL_KEY_TILE && d->key_mode != PL_KEY_TILE_CELL) return PL_EINVAL;
+    if (!finite_pos(d->c)) return PL_EINVAL;
+    if (d->nboxes < 1 || !d->boxes || d->nspecies < 1 || !d->species) return PL_EINVAL;
+    if (d->max_items < 1 || d->max_items > 4096) return PL_EINVAL;
+    if (d->max_np < 0 || d->max_np >= (int64_t)1 << 31) return PL_EINVAL;
+    if (d->block != 0 && (d->block < 64 || d->block > 512 || d->block % 64)) return PL_EINVAL;
+    for (int b = 0; b < d->nboxes; ++b) {
+        const pl_box_desc &x = d->boxes[b];
+        for (int a = 0; a < 3; ++a) {
+            if (x.n[a] < 1 || x.n[a] > kMaxN) return PL_EINVAL;
+            if (!finite_pos(x.dx[a])) return PL_EINVAL;
+            if (x.tile[a] < 0 || (x.tile[a] > 0 && x.n[a] % x.tile[a] != 0)) return PL_EINVAL;
+        }
+        if (d->ndim == 2 && (x.n[2] != 1 || x.tile[2] > 1)) return PL_EINVAL;
+        int zeros = (x.tile[0] == 0) + (x.tile[1] == 0) + (x.tile[2] == 0);
+        if (zeros != 0 && zeros != 3) return PL_EINVAL;
+    }
+    for (int s = 0; s < d->nspecies; ++s) {
+        const pl_species_desc &p = d->species[s];
+        if (p.kind != PL_LORENTZ && p.kind != PL_DUST && p.kind != PL_TRACER) return PL_EINVAL;
+        if (!finite_pos(p.m) || !isfinite(p.q) || !isfinite(p.weight)) return PL_EINVAL;
+        if (p.kind == PL_DUST && !finite_pos(p.t_stop)) return PL_EINVAL;
+    }
+    return PL_OK;
+}
+
+// Largest divisor of n that is <= want.
+int divisor_at_most(int n, int want)
+{
+    for (int t = std::min(n, want); t >= 1; --t)
+        if (n % t == 0) return t;
+    return 1;
+}
+
+void read_tune_cache(const char *path, int &block, int tile[3])
+{
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[64];
+    while (fscanf(f, "%63s", key) == 1) {
+        if (!strcmp(key, "block")) {
+            int v;
+            if (fscanf(f, "%d", &v) == 1 && v >= 64 && v <= 1024 && v % 64 == 0) block = v;
+        } else if (!strcmp(key, "tile")) {
+            int a, b, c;
+            if (fscanf(f, "%d %d %d", &a, &b, &c) == 3 && a > 0 && b > 0 && c > 0) {
+                tile[0] = a; tile[1] = b; tile[2] = c;
+            }
+        } else {
+            int ch;
+            while ((ch = fgetc(f)) != EOF && ch != '\n') {}
+        }
+    }
+    fclose(f);
+}
+
+void free_ctx(Ctx *c)
+{
+    if (!c) return;
+    for (auto &g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        if (g.table) (void)hipFree(g.table);
+    }
+    (void)hipFree(c->table);
+    (void)hipFree(c->counters);
+    (void)hipFree(c->errflags);
+    (void)hipFree(c->sums);
+    for (int k = 0; k < 2; ++k) {
+        (void)hipFree(c->keys[k]);
+        (void)hipFree(c->idx[k]);
+    }
+    (void)hipFree(c->hist);
+    (void)hipFree(c->hist_scan);
+    for (int k = 0; k < Ctx::kRing; ++k)
+        if (c->ring_ev[k]) (void)hipEventDestroy(c->ring_ev[k]);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+}
+
+// ---------------------------------------------------------------------------
+// Item validation and descriptor construction
+// ---------------------------------------------------------------------------
+
+enum Mode { MODE_STEP, MODE_DEPOSIT, MODE_QUERY };  // QUERY: sort, pack, sums
+
+pl_status make_desc(const Ctx *c, const pl_item &it, double dt, Mode mode, bool deposit, ItemDesc &D)
+{
+    const pl_init_desc &d = c->d;
+    if (it.box < 0 || it.box >= d.nboxes || it.species < 0 || it.species >= d.nspecies) return PL_EINVAL;
+    const pl_box_desc &bx = c->boxes[it.box];
+    const pl_species_desc &sp = c->species[it.species];
+    const pl_particles &p = it.p;
+    if (p.n < 0 || p.n > c->max_np) return PL_EINVAL;
+    if (p.cur != 0 && p.cur != 1) return PL_EINVAL;
+    const size_t es = d.prec == PL_F64 ? 8 : 4;
+    const int cur = p.cur;
+    const bool need = p.n > 0;
+    auto chk = [&](const void *ptr, size_t al, bool required) {
+        if (!ptr) return !required;
+        return aligned(ptr, al);
+    };
+    if (d.prec == PL_F32_OFFSET && !chk(p.cell[cur], 4, need)) return PL_EINVAL;
+    for (int a = 0; a < d.ndim; ++a)
+        if (!chk(p.x[cur][a], es, need)) return PL_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!chk(p.u[cur][a], es, need)) return PL_EINVAL;
+    if (!chk(p.w[cur], es, false)) return PL_EINVAL;
+    int nfp = (p.fp[0] != nullptr) + (p.fp[1] != nullptr) + (p.fp[2] != nullptr);
+    if (nfp != 0 && nfp != 3) return PL_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!chk(p.fp[a], es, false)) return PL_EINVAL;
+    if (d.algo == PL_ALGO_TILED && !chk(p.tile_start, 4, true)) return PL_EINVAL;
+
+    // fields the kind reads (only when pushing)
+    if (mode == MODE_STEP) {
+        if (sp.kind == PL_LORENTZ) {
+            for (int a = 0; a < 3; ++a)
+                if (!chk(it.f.E[a], 8, true) || !chk(it.f.B[a], 8, true)) return PL_EINVAL;
+        } else {
+            for (int a = 0; a < 3; ++a)
+                if (!chk(it.f.vg[a], 8, true)) return PL_EINVAL;
+        }
+    }
+    // moment channels the kind defines
+    const pl_moments &m = it.m;
+    int nJ = (m.J[0] != nullptr) + (m.J[1] != nullptr) + (m.J[2] != nullptr);
+    int nF = (m.F[0] != nullptr) + (m.F[1] != nullptr) + (m.F[2] != nullptr);
+    if ((nJ != 0 && nJ != 3) || (nF != 0 && nF != 3)) return PL_EINVAL;
+    double *M[kMaxCh] = {m.rho, m.J[0], m.J[1], m.J[2], m.F[0], m.F[1], m.F[2], m.eng};
+    for (int ch = 0; ch < kMaxCh; ++ch)
+        if (!chk(M[ch], 8, false)) return PL_EINVAL;
+    if (sp.kind == PL_TRACER && (m.rho || nJ || nF || m.eng)) return PL_EINVAL;
+    if (sp.kind == PL_DUST && (nJ || m.eng)) return PL_EINVAL;
+    if (mode == MODE_DEPOSIT) {
+        if (m.eng) return PL_EINVAL;
+        if (nF && nfp != 3) return PL_EINVAL;
+    }
+
+    memset(&D, 0, sizeof(D));
+    for (int a = 0; a < 3; ++a) {
+        D.n[a] = bx.n[a];
+        D.tile[a] = bx.tile[a];
+        D.ntile[a] = bx.n[a] / bx.tile[a];
+        D.dtdx[a] = dt / bx.dx[a];
+        D.dtdx_f[a] = (float)D.dtdx[a];
+    }
+    D.ntiles = D.ntile[0] * D.ntile[1] * D.ntile[2];
+    double dv = bx.dx[0] * bx.dx[1] * (d.ndim == 3 ? bx.dx[2] : 1.0);
+    D.inv_dv = 1.0 / dv;
+    D.kind = sp.kind;
+    D.q = sp.q;
+    D.m = sp.m;
+    D.wdef = sp.weight;
+    D.h = (sp.q / sp.m) * dt * 0.5;
+    D.inv_dt = dt != 0.0 ? 1.0 / dt : 0.0;
+    D.c2 = d.c * d.c;
+    D.inv_c2 = 1.0 / D.c2;
+    if (sp.kind == PL_DUST) {
+        D.decay = exp(-dt / sp.t_stop);
+        D.one_m_decay = -expm1(-dt / sp.t_stop);
+    }
+    D.np = (int)p.n;
+    D.cell = p.cell[cur];
+    for (int a = 0; a < 3; ++a) {
+        D.x[a] = a < d.ndim ? p.x[cur][a] : nullptr;
+        D.u[a] = p.u[cur][a];
+        D.fp[a] = p.fp[a];
+        D.E[a] = it.f.E[a];
+        D.B[a] = it.f.B[a];
+        D.vg[a] = it.f.vg[a];
+    }
+    D.w = p.w[cur];
+    D.tile_start = p.tile_start;
+    D.nslot = 0;
+    for (int ch = 0; ch < kMaxCh; ++ch) {
+        D.M[ch] = M[ch];
+        D.slot[ch] = (deposit && M[ch]) ? D.nslot++ : -1;
+    }
+    return PL_OK;
+}
+
+// Build the descriptor list of a call: validated, ordered largest first, with
+// work units assigned.  `order` maps table position -> caller index.
+pl_status build_table(Ctx *c, const pl_item *items, int nitems, double dt, Mode mode, bool deposit,
+                      std::vector<ItemDesc> &host, int &total_units)
+{
+    if (!items || nitems < 1 || nitems > c->d.max_items) return PL_EINVAL;
+    std::vector<ItemDesc> descs(nitems);
+    for (int i = 0; i < nitems; ++i) {
+        pl_status st = make_desc(c, items[i], dt, mode, deposit, descs[i]);
+        if (st != PL_OK) return st;
+        descs[i].psum = c->sums + 16 * i + 8;
+    }
+    // items must not share particle storage
+    for (int i = 0; i < nitems; ++i)
+        for (int j = i + 1; j < nitems; ++j)
+            if (descs[i].np > 0 && descs[j].np > 0 && descs[i].u[0] == descs[j].u[0]) return PL_EINVAL;
+    std::vector<int> order(nitems);
+    for (int i = 0; i < nitems; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return descs[a].np > descs[b].np; });
+    host.clear();
+    total_units = 0;
+    const bool tiled = c->d.algo == PL_ALGO_TILED;
+    const int chunk = c->block * 4;
+    for (int k = 0; k < nitems; ++k) {
+        ItemDesc D = descs[order[k]];
+        D.unit_begin = total_units;
+        D.chunk = chunk;
+        D.nunits = tiled ? D.ntiles : (D.np + chunk - 1) / chunk;
+        if (D.np == 0) D.nunits = 0;
+        total_units += D.nunits;
+        host.push_back(D);
+    }
+    return PL_OK;
+}
+
+// Stage the table through the pinned ring and queue its upload.
+pl_status upload_table(Ctx *c, const std::vector<ItemDesc> &host, ItemDesc *dst)
+{
+    int slot = c->ring_pos;
+    c->ring_pos = (c->ring_pos + 1) % Ctx::kRing;
+    PL_TRY_HIP(hipEventSynchronize(c->ring_ev[slot]));
+    ItemDesc *stage = c->pinned + (size_t)slot * c->d.max_items;
+    memcpy(stage, host.data(), host.size() * sizeof(ItemDesc));
+    PL_TRY_HIP(hipMemcpyAsync(dst, stage, host.size() * sizeof(ItemDesc), hipMemcpyHostToDevice, c->stream));
+    PL_TRY_HIP(hipEventRecord(c->ring_ev[slot], c->stream));
+    return PL_OK;
+}
+
+pl_status enqueue_step(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc> &host, int total_units,
+                       uint32_t flags, bool push, bool deposit)
+{
+    if (deposit && (flags & PL_ZERO_FIRST)) PL_TRY_HIP(launch_zero(c, host));
+    if (flags & PL_SUMS) PL_TRY_HIP(launch_zero_sums(c, c->sums, 16 * c->d.max_items));
+    hipError_t e = launch_step(c, table, host, (int)host.size(), total_units, flags, deposit, push);
+    if (e == hipErrorInvalidConfiguration) return PL_EUNSUPPORTED;
+    if (e != hipSuccess) return PL_EHIP;
+    return PL_OK;
+}
+
+uint64_t fnv1a(const void *p, size_t n, uint64_t h)
+{
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+pl_status run_call(Ctx *c, const pl_item *items, int nitems, double dt, uint32_t flags, Mode mode)
+{
+    const bool push = mode == MODE_STEP;
+    const bool deposit = mode == MODE_DEPOSIT || (flags & PL_FUSE_DEPOSIT);
+    std::vector<ItemDesc> host;
+    int total = 0;
+    pl_status st = build_table(c, items, nitems, dt, mode, deposit, host, total);
+    if (st != PL_OK) return st;
+
+    if (!(flags & PL_GRAPH)) {
+        st = upload_table(c, host, c->table);
+        if (st != PL_OK) return st;
+        return enqueue_step(c, c->table, host, total, flags, push, deposit);
+    }
+
+    if (!c->stream) return PL_EINVAL;   // the null stream cannot be captured
+    uint64_t key = fnv1a(host.data(), host.size() * sizeof(ItemDesc), 1469598103934665603ull);
+    uint32_t tag[2] = {flags, (uint32_t)mode};
+    key = fnv1a(tag, sizeof(tag), key);
+    c->use_clock++;
+    for (auto &g : c->graphs) {
+        if (g.valid && g.key == key && g.nitems == (int)host.size()) {
+            g.last_use = c->use_clock;
+            PL_TRY_HIP(hipGraphLaunch(g.exec, c->stream));
+            c->stats[1]++;
+            return PL_OK;
+        }
+    }
+    // record a new graph in the least recently used slot
+    GraphEntry *slot = &c->graphs[0];
+    for (auto &g : c->graphs) {
+        if (!g.valid) { slot = &g; break; }
+        if (g.last_use < slot->last_use) slot = &g;
+    }
+    if (slot->exec) { (void)hipGraphExecDestroy(slot->exec); slot->exec = nullptr; }
+    if (slot->graph) { (void)hipGraphDestroy(slot->graph); slot->graph = nullptr; }
+    slot->valid = false;
+    // the graph's own table: written now, read by every replay
+    PL_TRY_HIP(hipStreamSynchronize(c->stream));
+    PL_TRY_HIP(hipMemcpy(slot->table, host.data(), host.size() * sizeof(ItemDesc), hipMemcpyHostToDevice));
+    PL_TRY_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    pl_status est = enqueue_step(c, slot->table, host, total, flags, push, deposit);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(c->stream, &graph);
+    if (est != PL_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return est;
+    }
+    if (ce != hipSuccess) return PL_EHIP;
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return PL_EHIP;
+    }
+    slot->graph = graph;
+    slot->exec = exec;
+    slot->key = key;
+    slot->nitems = (int)host.size();
+    slot->valid = true;
+    slot->last_use = c->use_clock;
+    c->stats[2]++;
+    PL_TRY_HIP(hipGraphLaunch(exec, c->stream));
+    c->stats[1]++;
+    return PL_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Exported entry points
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d)
+{
+    if (!out) return PL_EINVAL;
+    *out = nullptr;
+    pl_status st = validate_desc(d);
+    if (st != PL_OK) return st;
+    Ctx *c = new (std::nothrow) Ctx();
+    if (!c) return PL_ENOMEM;
+    c->d = *d;
+    c->d.tune_cache = nullptr;
+    c->boxes.assign(d->boxes, d->boxes + d->nboxes);
+    c->species.assign(d->species, d->species + d->nspecies);
+    c->d.boxes = c->boxes.data();
+    c->d.species = c->species.data();
+    c->stream = (hipStream_t)d->stream;
+    c->max_np = d->max_np;
+
+    int tuned_block = 256, tuned_tile[3] = {8, 8, 8};
+    if (d->prec == PL_F64 && d->algo == PL_ALGO_TILED) { tuned_tile[1] = 4; tuned_tile[2] = 4; }
+    read_tune_cache(d->tune_cache, tuned_block, tuned_tile);
+    c->block = d->block ? d->block : tuned_block;
+    for (auto &b : c->boxes) {
+        if (b.tile[0] == 0) {
+            for (int a = 0; a < 3; ++a) b.tile[a] = divisor_at_most(b.n[a], tuned_tile[a]);
+            if (d->ndim == 2) b.tile[2] = 1;
+        }
+        c->max_ntiles = std::max(c->max_ntiles, (b.n[0] / b.tile[0]) * (b.n[1] / b.tile[1]) * (b.n[2] / b.tile[2]));
+    }
+
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess) {
+        delete c;
+        return PL_EHIP;
+    }
+    if (c->num_cu < 1) c->num_cu = 1;
+
+    const size_t mi = (size_t)d->max_items;
+    const size_t np = (size_t)std::max<int64_t>(d->max_np, 1);
+    const size_t nblocks = (np + 8191) / 8192;
+    c->hist_cap = (int64_t)(256 * nblocks + 1024);
+    bool ok = hipMalloc(&c->table, mi * sizeof(ItemDesc)) == hipSuccess &&
+              hipMalloc(&c->counters, 64 * sizeof(unsigned)) == hipSuccess &&
+              hipMalloc(&c->errflags, 4 * sizeof(int)) == hipSuccess &&
+              hipMalloc(&c->sums, 16 * mi * sizeof(double)) == hipSuccess &&
+              hipMalloc(&c->hist, (size_t)c->hist_cap * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc(&c->hist_scan, (size_t)c->hist_cap * sizeof(uint32_t)) == hipSuccess &&
+              hipHostMalloc(&c->pinned, Ctx::kRing * mi * sizeof(ItemDesc), hipHostMallocDefault) == hipSuccess;
+    for (int k = 0; ok && k < 2; ++k)
+        ok = hipMalloc(&c->keys[k], np * sizeof(uint32_t)) == hipSuccess &&
+             hipMalloc(&c->idx[k], np * sizeof(uint32_t)) == hipSuccess;
+    for (int k = 0; ok && k < Ctx::kGraphs; ++k)
+        ok = hipMalloc(&c->graphs[k].table, mi * sizeof(ItemDesc)) == hipSuccess;
+    for (int k = 0; ok && k < Ctx::kRing; ++k)
+        ok = hipEventCreateWithFlags(&c->ring_ev[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        free_ctx(c);
+        return PL_ENOMEM;
+    }
+    if (hipMemset(c->counters, 0, 64 * sizeof(unsigned)) != hipSuccess ||
+        hipMemset(c->errflags, 0, 4 * sizeof(int)) != hipSuccess ||
+        hipMemset(c->sums, 0, 16 * mi * sizeof(double)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        free_ctx(c);
+        return PL_EHIP;
+    }
+    *out = reinterpret_cast<pl_ctx *>(c);
+    return PL_OK;
+}
+
+pl_status pl_part_gather_push(pl_ctx *ctx, pl_item *items, int nitems, double dt, uint32_t flags)
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || !isfinite(dt) || dt == 0.0) return PL_EINVAL;
+    if (flags & ~(PL_FUSE_DEPOSIT | PL_ZERO_FIRST | PL_GRAPH | PL_SUMS)) return PL_EINVAL;
+    return run_call(c, items, nitems, dt, flags, MODE_STEP);
+}
+
+pl_status pl_part_deposit(pl_ctx *ctx, const pl_item *items, int nitems, uint32_t flags)
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c) return PL_EINVAL;
+    if (flags & ~(PL_ZERO_FIRST | PL_GRAPH)) return PL_EINVAL;
+    return run_call(c, items, nitems, 0.0, flags, MODE_DEPOSIT);
+}
+
+pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems)
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || !items || nitems < 1 || nitems > c->d.max_items) return PL_EINVAL;
+    const bool f64 = c->d.prec == PL_F64;
+    const size_t es = f64 ? 8 : 4;
+    std::vector<SortArgs> args(nitems);
+    for (int i = 0; i < nitems; ++i) {
+        const pl_item &it = items[i];
+        ItemDesc D;
+        pl_status st = make_desc(c, it, 1.0, MODE_QUERY, false, D);
+        if (st != PL_OK) return st;
+        const pl_particles &p = it.p;
+        if (!p.tile_start || !aligned(p.tile_start, 4)) return PL_EINVAL;
+        const int cur = p.cur, nxt = 1 - p.cur;
+        SortArgs &a = args[i];
+        memset(&a, 0, sizeof(a));
+        a.prec = c->d.prec;
+        a.ndim = c->d.ndim;
+        a.key_mode = c->d.key_mode;
+        for (int k = 0; k < 3; ++k) {
+            a.n[k] = D.n[k];
+            a.tile[k] = D.tile[k];
+            a.x[k] = (f64 && k < c->d.ndim) ? (const double *)p.x[cur][k] : nullptr;
+        }
+        a.np = D.np;
+        a.ntiles = D.ntiles;
+        a.cell = p.cell[cur];
+        a.tile_start = p.tile_start;
+        auto add = [&](const void *s, void *dd, int esz) -> bool {
+            if (!s) return true;
+            if (!dd || !aligned(dd, (size_t)esz) || a.narrays >= SortArgs::kMaxArrays) return false;
+            a.src[a.narrays] = s;
+            a.dst[a.narrays] = dd;
+            a.esize[a.narrays] = esz;
+            a.narrays++;
+            return true;
+        };
+        bool ok = true;
+        if (!f64) ok = ok && add(p.cell[cur], p.cell[nxt], 4);
+        for (int k = 0; k < c->d.ndim; ++k) ok = ok && add(p.x[cur][k], p.x[nxt][k], (int)es);
+        for (int k = 0; k < 3; ++k) ok = ok && add(p.u[cur][k], p.u[nxt][k], (int)es);
+        ok = ok && add(p.w[cur], p.w[nxt], (int)es);
+        ok = ok && add(p.id[cur], p.id[nxt], 8);
+        if (p.id[cur] && !aligned(p.id[cur], 8)) ok = false;
+        if (!ok) return PL_EINVAL;
+    }
+    for (int i = 0; i < nitems; ++i) {
+        if (launch_sort(c, args[i]) != hipSuccess) return PL_EHIP;
+        items[i].p.cur = 1 - items[i].p.cur;
+        c->stats[3]++;
+    }
+    return PL_OK;
+}
+
+pl_status pl_part_pack(pl_ctx *ctx, const pl_item *item, const double *x[3], const double *u[3])
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || !item || !x || !u) return PL_EINVAL;
+    ItemDesc D;
+    pl_status st = make_desc(c, *item, 1.0, MODE_QUERY, false, D);
+    if (st != PL_OK) return st;
+    const double *xs[3] = {nullptr, nullptr, nullptr}, *us[3];
+    for (int a = 0; a < 3; ++a) {
+        if (a < c->d.ndim) {
+            if ((D.np > 0 && !x[a]) || !aligned(x[a], 8)) return PL_EINVAL;
+            xs[a] = x[a];
+        }
+        if ((D.np > 0 && !u[a]) || !aligned(u[a], 8)) return PL_EINVAL;
+        us[a] = u[a];
+    }
+    return launch_pack(c, D, c->d.prec, c->d.ndim, xs, us) == hipSuccess ? PL_OK : PL_EHIP;
+}
+
+pl_status pl_part_unpack(pl_ctx *ctx, const pl_item *item, double *x[3], double *u[3])
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || !item || !x || !u) return PL_EINVAL;
+    ItemDesc D;
+    pl_status st = make_desc(c, *item, 1.0, MODE_QUERY, false, D);
+    if (st != PL_OK) return st;
+    double *xs[3] = {nullptr, nullptr, nullptr}, *us[3];
+    for (int a = 0; a < 3; ++a) {
+        if (a < c->d.ndim) {
+            if ((D.np > 0 && !x[a]) || !aligned(x[a], 8)) return PL_EINVAL;
+            xs[a] = x[a];
+        }
+        if ((D.np > 0 && !u[a]) || !aligned(u[a], 8)) return PL_EINVAL;
+        us[a] = u[a];
+    }
+    return launch_unpack(c, D, c->d.prec, c->d.ndim, xs, us) == hipSuccess ? PL_OK : PL_EHIP;
+}
+
+pl_status pl_part_sums(pl_ctx *ctx, const pl_item *items, int nitems, double *out)
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || !items || !out || nitems < 1 || nitems > c->d.max_items) return PL_EINVAL;
+    std::vector<ItemDesc> descs(nitems);
+    for (int i = 0; i < nitems; ++i) {
+        pl_status st = make_desc(c, items[i], 1.0, MODE_QUERY, true, descs[i]);
+        if (st != PL_OK) return st;
+    }
+    for (int i = 0; i < nitems; ++i) {
+        PL_TRY_HIP(launch_zero_sums(c, c->sums + 16 * i, 8));
+        PL_TRY_HIP(launch_grid_sums(c, descs[i], c->sums + 16 * i));
+    }
+    PL_TRY_HIP(hipMemcpyAsync(out, c->sums, 16 * (size_t)nitems * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    PL_TRY_HIP(hipStreamSynchronize(c->stream));
+    return PL_OK;
+}
+
+pl_status pl_part_sync(pl_ctx *ctx)
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c) return PL_EINVAL;
+    PL_TRY_HIP(hipStreamSynchronize(c->stream));
+    int flags = 0;
+    PL_TRY_HIP(hipMemcpy(&flags, c->errflags, sizeof(int), hipMemcpyDeviceToHost));
+    if (flags) PL_TRY_HIP(hipMemset(c->errflags, 0, sizeof(int)));
+    if (flags & ERR_NONFINITE) return PL_ENONFINITE;
+    if (flags & ERR_CFL) return PL_ECFL;
+    return PL_OK;
+}
+
+pl_status pl_part_set_stream(pl_ctx *ctx, void *stream)
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c) return PL_EINVAL;
+    PL_TRY_HIP(hipStreamSynchronize(c->stream));
+    for (auto &g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        g.exec = nullptr;
+        g.graph = nullptr;
+        g.valid = false;
+    }
+    c->stream = (hipStream_t)stream;
+    return PL_OK;
+}
+
+pl_status pl_part_stats(pl_ctx *ctx, int64_t out[4])
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || !out) return PL_EINVAL;
+    for (int k = 0; k < 4; ++k) out[k] = c->stats[k];
+    return PL_OK;
+}
+
+void pl_part_finalize(pl_ctx *ctx)
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_ctx(c);
+}
+
+const char *pl_status_string(pl_status s)
+{
+    switch (s) {
+    case PL_OK: return "success";
+    case PL_EINVAL: return "invalid argument";
+    case PL_ENOMEM: return "out of memory";
+    case PL_EHIP: return "HIP runtime error";
+    case PL_EUNSUPPORTED: return "unsupported request";
+    case PL_ECFL: return "a particle moved a full cell or more in one step";
+    case PL_ENONFINITE: return "non-finite or out-of-range particle coordinate";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Internal declarations shared by the HIP sources of libpl.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/pl.h"
+
+namespace pl {
+
+constexpr int kMaxCh = 8;            // rho, J0, J1, J2, F0, F1, F2, eng
+constexpr int kCellBits = 10;        // packed cell: 10 bits per dimension
+constexpr int kMaxN = 1 << kCellBits;
+
+enum Channel { CH_RHO = 0, CH_J0 = 1, CH_F0 = 4, CH_ENG = 7 };
+
+// Latched device-side error bits.
+enum ErrBit { ERR_CFL = 1, ERR_NONFINITE = 2 };
+
+// Everything a kernel needs to know about one item of a call.  Built on the
+// host for every call, uploaded into the context's item table.
+struct ItemDesc {
+    // box
+    int n[3];
+    int tile[3];
+    int ntile[3];
+    int ntiles;
+    double inv_dv;
+    double dtdx[3];          // dt / dx per dimension
+    float dtdx_f[3];
+    // species
+    int kind;
+    double h;                // (q/m) dt / 2
+    double q, m, wdef;
+    double decay;            // dust: exp(-dt/t_stop)
+    double one_m_decay;      // dust: 1 - exp(-dt/t_stop)
+    double inv_dt;
+    double c2, inv_c2;
+    // particles, current buffer set
+    int np;
+    uint32_t *cell;
+    void *x[3];
+    void *u[3];
+    void *w;
+    void *fp[3];
+    int32_t *tile_start;
+    // fields
+    const double *E[3];
+    const double *B[3];
+    const double *vg[3];
+    // moments
+    double *M[kMaxCh];
+    int slot[kMaxCh];        // LDS slot of each active channel, -1 if inactive
+    int nslot;
+    // work decomposition
+    int unit_begin;          // first global work unit of this item
+    int nunits;
+    int chunk;               // particles per unit (plain algorithm)
+    double *psum;            // particle-side sums, 8 doubles
+};
+
+struct GraphEntry {
+    uint64_t key = 0;
+    bool valid = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ItemDesc *table = nullptr;       // device table owned by this graph
+    int nitems = 0;
+    uint64_t last_use = 0;
+};
+
+struct Ctx {
+    pl_init_desc d;
+    std::vector<pl_box_desc> boxes;
+    std::vector<pl_species_desc> species;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int num_cu = 0;
+    int block = 256;
+    int lds_max = 65536;
+
+    // device scratch
+    ItemDesc *table = nullptr;       // max_items descriptors for non-graph calls
+    unsigned *counters = nullptr;    // work counters: 2 per launch stage
+    int *errflags = nullptr;         // latched error bits
+    double *sums = nullptr;          // max_items * 16
+    uint32_t *keys[2] = {nullptr, nullptr};
+    uint32_t *idx[2] = {nullptr, nullptr};
+    uint32_t *hist = nullptr;        // radix digit counts
+    uint32_t *hist_scan = nullptr;
+    int64_t hist_cap = 0;
+    int64_t max_np = 0;
+    int max_ntiles = 0;
+
+    // pinned staging ring for item tables
+    static constexpr int kRing = 8;
+    ItemDesc *pinned = nullptr;      // kRing * max_items
+    hipEvent_t ring_ev[kRing] = {};
+    int ring_pos = 0;
+
+    // graphs
+    static constexpr int kGraphs = 8;
+    GraphEntry graphs[kGraphs];
+    uint64_t use_clock = 0;
+
+    int64_t stats[4] = {0, 0, 0, 0}; // launches, graph replays, graph captures, sorts
+};
+
+// Kernel launchers (k_step.hip)
+hipError_t launch_step(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc> &host, int nitems,
+                       int total_units, unsigned flags, bool deposit, bool push);
+hipError_t launch_zero(Ctx *c, const std::vector<ItemDesc> &host);
+hipError_t launch_zero_sums(Ctx *c, double *sums, int n);
+hipError_t launch_grid_sums(Ctx *c, const ItemDesc &it, double *out8);
+hipError_t launch_pack(Ctx *c, const ItemDesc &it, int prec, int ndim, const double *x[3], const double *u[3]);
+hipError_t launch_unpack(Ctx *c, const ItemDesc &it, int prec, int ndim, double *x[3], double *u[3]);
+
+// Sort (k_sort.hip)
+struct SortArgs {
+    int prec, ndim, key_mode;
+    int n[3], tile[3];
+    int np;
+    int ntiles;
+    const uint32_t *cell;            // F32_OFFSET
+    const double *x[3];              // F64
+    // source and destination arrays (element sizes given): cell, 3 x, 3 u, w, id
+    static constexpr int kMaxArrays = 12;
+    const void *src[kMaxArrays];
+    void *dst[kMaxArrays];
+    int esize[kMaxArrays];
+    int narrays;
+    int32_t *tile_start;
+};
+hipError_t launch_sort(Ctx *c, const SortArgs &a);
+
+}  // namespace pl

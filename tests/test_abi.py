@@ -1,0 +1,134 @@
+"""The C-ABI library loads, exports every symbol include/pl.h declares, and its
+ctypes structures match the C layout.  Host-side argument validation is
+exercised on paths that return before any HIP call (no GPU needed)."""
+
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2602_23434_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pl.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pl_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2602_23434_amd import build
+        build.build()
+    return B.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "pl_part_init" in names and "pl_part_sort" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(B.EXPORTS) == names
+
+
+def test_status_strings(lib):
+    for s in range(7):
+        assert B.pl_status_string(s) not in ("", "unknown status")
+    assert B.pl_status_string(99) == "unknown status"
+
+
+_PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "pl.h"
+#define S(t) printf(#t " %zu\n", sizeof(t));
+#define O(t, f) printf(#t "." #f " %zu\n", offsetof(t, f));
+int main(void) {
+  S(pl_box_desc) O(pl_box_desc, dx) O(pl_box_desc, tile)
+  S(pl_species_desc) O(pl_species_desc, q) O(pl_species_desc, t_stop)
+  S(pl_init_desc) O(pl_init_desc, c) O(pl_init_desc, boxes) O(pl_init_desc, species) O(pl_init_desc, max_np)
+  O(pl_init_desc, block) O(pl_init_desc, stream) O(pl_init_desc, tune_cache)
+  S(pl_particles) O(pl_particles, cur) O(pl_particles, cell) O(pl_particles, x) O(pl_particles, u)
+  O(pl_particles, w) O(pl_particles, id) O(pl_particles, fp) O(pl_particles, tile_start)
+  S(pl_fields) O(pl_fields, B) O(pl_fields, vg)
+  S(pl_moments) O(pl_moments, J) O(pl_moments, F) O(pl_moments, eng)
+  S(pl_item) O(pl_item, p) O(pl_item, f) O(pl_item, m)
+  return 0;
+}
+"""
+
+
+def test_struct_layout_matches_c():
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(src, "w").write(_PROBE)
+        subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    for line in out.strip().splitlines():
+        name, val = line.split()
+        val = int(val)
+        if "." in name:
+            t, f = name.split(".")
+            assert getattr(getattr(B, t), f).offset == val, name
+        else:
+            assert C.sizeof(getattr(B, name)) == val, name
+
+
+def _desc(**kw):
+    boxes = (B.pl_box_desc * 1)()
+    for a in range(3):
+        boxes[0].n[a] = 8
+        boxes[0].dx[a] = 1.0
+        boxes[0].tile[a] = 4
+    sp = (B.pl_species_desc * 1)()
+    sp[0].kind = B.PL_LORENTZ
+    sp[0].q = sp[0].m = sp[0].weight = 1.0
+    d = B.pl_init_desc()
+    d.ndim, d.prec, d.shape, d.algo, d.key_mode = 3, B.PL_F64, B.PL_TSC, B.PL_ALGO_PLAIN, B.PL_KEY_TILE
+    d.c = 1.0
+    d.nboxes, d.boxes, d.nspecies, d.species = 1, boxes, 1, sp
+    d.max_items, d.max_np, d.block = 1, 100, 0
+    d._keep = (boxes, sp)
+    for k, v in kw.items():
+        if k in ("n", "tile", "dx"):
+            for a in range(3):
+                getattr(boxes[0], k)[a] = v[a]
+        elif k in ("kind", "m", "t_stop", "q"):
+            setattr(sp[0], k, v)
+        else:
+            setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ndim=4), dict(prec=7), dict(shape=0), dict(algo=3), dict(key_mode=5), dict(c=0.0),
+    dict(c=float("inf")), dict(max_items=0), dict(max_np=-1), dict(max_np=1 << 31), dict(block=100),
+    dict(block=1024), dict(n=(8, 8, 2000)), dict(n=(0, 8, 8)), dict(tile=(3, 4, 4)), dict(tile=(0, 4, 4)),
+    dict(dx=(1.0, -1.0, 1.0)), dict(kind=9), dict(m=0.0), dict(kind=B.PL_DUST, t_stop=0.0),
+    dict(ndim=2),          # 2D with n[2] = 8
+    dict(nboxes=0),
+])
+def test_init_rejects_bad_descriptions(lib, bad):
+    d = _desc(**bad)
+    ctx = C.c_void_p()
+    st = lib.pl_part_init(C.byref(ctx), C.byref(d))
+    assert st == B.PL_EINVAL
+    assert not ctx.value
+
+
+def test_null_context_calls_are_rejected(lib):
+    item = B.pl_item()
+    assert lib.pl_part_gather_push(None, C.byref(item), 1, 0.05, 0) == B.PL_EINVAL
+    assert lib.pl_part_deposit(None, C.byref(item), 1, 0) == B.PL_EINVAL
+    assert lib.pl_part_sort(None, C.byref(item), 1) == B.PL_EINVAL
+    assert lib.pl_part_sync(None) == B.PL_EINVAL
+    assert lib.pl_part_init(None, None) == B.PL_EINVAL
+    lib.pl_part_finalize(None)
