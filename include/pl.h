@@ -79,6 +79,10 @@ typedef int pl_status;
 
 #define PL_KEY_TILE       0  /* sort by tile */
 #define PL_KEY_TILE_CELL  1  /* sort by tile, then by cell inside the tile (x fastest) */
+#define PL_KEY_TILE_RANK  2  /* sort by tile, then by rank among the particles of the same cell
+                                (0 for the first in array order, ...), then by cell: consecutive
+                                particles lie in distinct cells.  Ranks of 2^rb - 1 and above share
+                                one level, rb = min(10, 32 - tile bits - cell-in-tile bits) >= 3 */
 
 /* flags of pl_part_gather_push / pl_part_deposit */
 #define PL_FUSE_DEPOSIT  (1u << 0)  /* gather_push also deposits at the new positions */
@@ -105,8 +109,8 @@ typedef struct {
     int ndim;                        /* 2 or 3, for every box of the context */
     int prec;                        /* PL_F64 or PL_F32_OFFSET */
     int shape;                       /* PL_CIC or PL_TSC */
-    int algo;                        /* PL_ALGO_PLAIN (PL_F64 only) or PL_ALGO_TILED */
-    int key_mode;                    /* PL_KEY_TILE or PL_KEY_TILE_CELL */
+    int algo;                        /* PL_ALGO_PLAIN or PL_ALGO_TILED */
+    int key_mode;                    /* PL_KEY_TILE, PL_KEY_TILE_CELL or PL_KEY_TILE_RANK */
     double c;                        /* speed of light in code units (> 0) */
     int nboxes;
     const pl_box_desc *boxes;        /* host array, copied */

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "liborc.so")
 
 CIC, TSC = 1, 2
 LORENTZ, DUST, TRACER = 0, 1, 2
-KEY_TILE, KEY_TILE_CELL = 0, 1
+KEY_TILE, KEY_TILE_CELL, KEY_TILE_RANK = 0, 1, 2
 KINDS = {"lorentz": LORENTZ, "dust": DUST, "tracer": TRACER}
 SHAPES = {"cic": CIC, "tsc": TSC}
 
@@ -84,6 +84,9 @@ def lib():
                                               C.POINTER(C.c_uint32)]
         L.orc_split_position.restype = None
         L.orc_split_position.argtypes = [C.POINTER(_Box), _P, C.POINTER(C.c_long), C.POINTER(C.c_float)]
+        L.orc_rank_keys.restype = C.c_int
+        L.orc_rank_keys.argtypes = [C.POINTER(_Box), C.c_int * 3, C.c_long, C.POINTER(C.c_long),
+                                    C.POINTER(C.c_long), C.POINTER(C.c_long), C.POINTER(C.c_uint32)]
         L.orc_num_threads.restype = C.c_int
         L.orc_num_threads.argtypes = []
         L.orc_stable_sort_perm.restype = None
@@ -206,6 +209,30 @@ def keys_from_positions(ndim, n, tile, key_mode, x):
     lib().orc_keys_from_positions(C.byref(b), t, key_mode, npart, xs,
                                   keys.ctypes.data_as(C.POINTER(C.c_uint32)))
     return keys
+
+
+def rank_keys(ndim, n, tile, cells):
+    """Rank-interleaved sort keys from integer cells (3, np); returns (keys, rank_bits)."""
+    b = _box(ndim, n)
+    t = (C.c_int * 3)(*tile)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    npart = cells.shape[1]
+    keys = np.zeros(npart, dtype=np.uint32)
+    lp = C.POINTER(C.c_long)
+    c = [np.ascontiguousarray(cells[d]) for d in range(3)]
+    rb = lib().orc_rank_keys(C.byref(b), t, npart, c[0].ctypes.data_as(lp), c[1].ctypes.data_as(lp),
+                             c[2].ctypes.data_as(lp), keys.ctypes.data_as(C.POINTER(C.c_uint32)))
+    return keys, rb
+
+
+def cells_of_positions(ndim, n, x):
+    """Integer cells floor(x) of float64 grid positions (after the periodic wrap)."""
+    cells = np.zeros((3, x.shape[1]), dtype=np.int64)
+    for d in range(ndim):
+        v = np.mod(x[d], n[d])
+        v = np.where(v >= n[d], 0.0, v)
+        cells[d] = np.floor(v).astype(np.int64)
+    return cells
 
 
 def split_positions(ndim, n, x):

@@ -310,6 +310,38 @@ void orc_keys_from_positions(const orc_box *b, const int tile[3], int key_mode, 
     }
 }
 
+static int bits_for(long count)
+{
+    int b = 0;
+    while ((1L << b) < count) ++b;
+    return b;
+}
+
+int orc_rank_keys(const orc_box *b, const int tile[3], long np, const long *ci, const long *cj, const long *ck,
+                  uint32_t *key)
+{
+    long ntiles = (long)(b->n[0] / tile[0]) * (b->n[1] / tile[1]) * (b->n[2] / tile[2]);
+    long per_tile = (long)tile[0] * tile[1] * tile[2];
+    int tb = bits_for(ntiles), cb = bits_for(per_tile);
+    int rb = 32 - tb - cb;
+    if (rb > 10) rb = 10;
+    if (rb < 3) return -1;
+    long ncells = (long)b->n[0] * b->n[1] * b->n[2];
+    long *seen = (long *)calloc((size_t)ncells, sizeof(long));
+    long rmax = (1L << rb) - 1;
+    for (long p = 0; p < np; ++p) {
+        long c = ci[p] + (long)b->n[0] * (cj[p] + (long)b->n[1] * ck[p]);
+        long rank = seen[c]++;
+        if (rank > rmax) rank = rmax;
+        uint32_t tk = orc_tile_key(b, tile, ORC_KEY_TILE, ci[p], cj[p], ck[p]);
+        uint32_t full = orc_tile_key(b, tile, ORC_KEY_TILE_CELL, ci[p], cj[p], ck[p]);
+        uint32_t local = full - tk * (uint32_t)per_tile;
+        key[p] = (tk << (rb + cb)) | ((uint32_t)rank << cb) | local;
+    }
+    free(seen);
+    return rb;
+}
+
 /*
  * Compact position: cell index plus the single-precision offset from the cell
  * centre.  If the offset rounds up to +1/2 the particle belongs to the next

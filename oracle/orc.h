@@ -23,7 +23,7 @@ extern "C" {
 
 enum { ORC_CIC = 1, ORC_TSC = 2 };
 enum { ORC_LORENTZ = 0, ORC_DUST = 1, ORC_TRACER = 2 };
-enum { ORC_KEY_TILE = 0, ORC_KEY_TILE_CELL = 1 };
+enum { ORC_KEY_TILE = 0, ORC_KEY_TILE_CELL = 1, ORC_KEY_TILE_RANK = 2 };
 
 typedef struct {
     int ndim;        /* 2 or 3; in 2D n[2] == 1 and the z coordinate is ignored */
@@ -69,6 +69,17 @@ uint32_t orc_tile_key(const orc_box *b, const int tile[3], int key_mode, long i,
 /* Keys of np particles from grid positions (cell = floor of each coordinate). */
 void orc_keys_from_positions(const orc_box *b, const int tile[3], int key_mode, long np,
                              double *x[3], uint32_t *key);
+
+/* Rank-interleaved keys from cells (i, j, k) given per particle: within a tile,
+ * particles are ordered first by their rank among earlier particles of the same
+ * cell (0 for the first particle of a cell in array order, 1 for the second,
+ * ...; ranks above 2^rank_bits - 1 share the last level), then by the cell's
+ * place in the tile (x fastest).  key = tile << (rank_bits + cell_bits)
+ * | rank << cell_bits | local, cell_bits = bits to number the cells of a tile,
+ * rank_bits = min(10, 32 - tile_bits - cell_bits).  Returns rank_bits, or -1
+ * when fewer than 3 bits are left for the rank. */
+int orc_rank_keys(const orc_box *b, const int tile[3], long np, const long *ci, const long *cj, const long *ck,
+                  uint32_t *key);
 
 /* Split grid position x into a cell index and a single-precision offset from
  * the cell centre in [-1/2, 1/2), per dimension (the compact position form). */

@@ -9,9 +9,9 @@ TURB_NP = 1 << 24
 CHANNELS = ["rho", "J0", "J1", "J2", "F0", "F1", "F2"]
 STEP_FLAGS = B.PL_FUSE_DEPOSIT | B.PL_ZERO_FIRST | B.PL_GRAPH
 
-F32_TILED = dict(prec=B.PL_F32_OFFSET, algo=B.PL_ALGO_TILED, key_mode=B.PL_KEY_TILE_CELL, tile=(8, 8, 8), block=512,
+F32_TILED = dict(prec=B.PL_F32_OFFSET, algo=B.PL_ALGO_TILED, key_mode=B.PL_KEY_TILE_RANK, tile=(8, 8, 8), block=512,
                  channels=CHANNELS, eng=False)
 F64_PLAIN = dict(prec=B.PL_F64, algo=B.PL_ALGO_PLAIN, key_mode=B.PL_KEY_TILE, tile=None, block=256,
                  channels=CHANNELS, eng=False)
-F64_TILED = dict(prec=B.PL_F64, algo=B.PL_ALGO_TILED, key_mode=B.PL_KEY_TILE_CELL, tile=(8, 8, 4), block=512,
+F64_TILED = dict(prec=B.PL_F64, algo=B.PL_ALGO_TILED, key_mode=B.PL_KEY_TILE_RANK, tile=(8, 8, 4), block=512,
                  channels=CHANNELS, eng=False)

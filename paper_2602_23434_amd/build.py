@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpl.so")
-SOURCES = ["pl_api.hip", "k_step.hip", "k_sort.hip"]
+SOURCES = ["pl_api.hip", "k_util.hip", "k_step_f32.hip", "k_step_f64.hip", "k_sort.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -29,21 +29,36 @@ FLAGS = [
 ]
 
 
-def build(verbose=False, extra=()):
-    objs = []
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + list(extra) + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libpl.so")
-    if verbose and r.stderr.strip():
+        raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
+    if verbose:
         # the host pass does not know the packed-fp32 feature: harmless
-        lines = [l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l]
+        lines = [l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and "--hip-link" not in l]
         if lines:
             sys.stderr.write("\n".join(lines) + "\n")
+
+
+def build(verbose=False, extra=(), jobs=None):
+    """Compile every source to an object in parallel, then link libpl.so."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    objs, cmds = [], []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        objs.append(obj)
+        cmds.append([HIPCC] + compile_flags + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj])
+    jobs = jobs or min(len(cmds), os.cpu_count() or 4, 16)
+    with ThreadPoolExecutor(jobs) as ex:
+        list(ex.map(lambda c: _run(c, verbose), cmds))
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,7 +1,8 @@
 // Stable cell-tile sort for gfx950.
 //
-// key(p) = tile of the particle's cell (or tile * cells_per_tile + cell in
-// tile).  The permutation is the stable one (ties keep their order), built by
+// key(p) = tile of the particle's cell, or tile * cells_per_tile + cell in
+// tile, or (rank-interleaved) tile, rank of the particle among the particles
+// of its cell, cell in tile.  The permutation is the stable one (ties keep their order), built by
 // least-significant-digit radix sort on (key, source index) pairs with 8-bit
 // digits: per pass a digit histogram per block, an exclusive scan in
 // digit-major order, and a scatter in which every wave ranks its 64 elements
@@ -203,20 +204,75 @@ __global__ void k_permute(const uint32_t *perm, int np, const void *src, void *d
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np; r += gridDim.x * blockDim.x) d[r] = s[perm[r]];
 }
 
-__global__ void k_tile_start(const uint32_t *keys, int np, int per_tile, int ntiles, int32_t *ts)
+__global__ void k_tile_start(const uint32_t *keys, int np, int shift, int per_tile, int ntiles, int32_t *ts)
 {
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np; r += gridDim.x * blockDim.x) {
-        int t = (int)(keys[r] / (uint32_t)per_tile);
-        int prev = r > 0 ? (int)(keys[r - 1] / (uint32_t)per_tile) : -1;
+        int t = (int)((keys[r] >> shift) / (uint32_t)per_tile);
+        int prev = r > 0 ? (int)((keys[r - 1] >> shift) / (uint32_t)per_tile) : -1;
         for (int q = prev + 1; q <= t; ++q) ts[q] = r;
         if (r == np - 1)
             for (int q = t + 1; q <= ntiles; ++q) ts[q] = np;
     }
 }
 
+// First sorted position of every cell (keys sorted by tile * cells_per_tile +
+// cell in tile); cells without particles are never read.
+__global__ void k_cell_start(const uint32_t *keys, int np, int32_t *cs)
+{
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np; r += gridDim.x * blockDim.x)
+        if (r == 0 || keys[r] != keys[r - 1]) cs[keys[r]] = r;
+}
+
+// Rank-interleaved key of sorted position r: its rank among the particles of
+// its cell (positions are in stable order, so this is the number of earlier
+// particles of the same cell), capped at 2^rank_bits - 1, between tile and cell.
+__global__ void k_rank_keys(uint32_t *keys, int np, const int32_t *cs, int cell_bits, int rank_bits)
+{
+    const uint32_t cmask = (1u << cell_bits) - 1u, rmax = (1u << rank_bits) - 1u;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np; r += gridDim.x * blockDim.x) {
+        uint32_t k = keys[r];
+        uint32_t rank = min((uint32_t)(r - cs[k]), rmax);
+        uint32_t tile = k >> cell_bits, local = k & cmask;
+        keys[r] = (tile << (rank_bits + cell_bits)) | (rank << cell_bits) | local;
+    }
+}
+
 __global__ void k_fill_i32(int32_t *p, int n, int v)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+static int bits_for(uint64_t count)
+{
+    int b = 0;
+    while (b < 32 && ((uint64_t)1 << b) < count) ++b;
+    return b;
+}
+
+// LSD radix passes over the low `bits` bits of keys[src] with indices idx[src]
+// (identity when `identity`); returns the buffer index holding the result.
+static int radix_passes(Ctx *c, int np, int src, bool identity, int bits)
+{
+    hipStream_t s = c->stream;
+    const int npass = std::max(1, (bits + 7) / 8);
+    const int nblocks = (np + kPerBlock - 1) / kPerBlock;
+    const long m = 256L * nblocks;
+    const long seg = (m + kScanBlocks - 1) / kScanBlocks;
+    const int nparts = (int)((m + seg - 1) / seg);
+    uint32_t *part = c->hist_scan + m;
+    for (int pass = 0; pass < npass; ++pass) {
+        int shift = 8 * pass;
+        hipLaunchKernelGGL(k_hist, dim3(nblocks), dim3(kSortThreads), 0, s, c->keys[src], np, shift, nblocks, c->hist);
+        hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(256), 0, s, c->hist, m, seg, part);
+        hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanBlocks), 0, s, part, nparts);
+        hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(256), 0, s, c->hist, m, seg, part, c->hist_scan);
+        hipLaunchKernelGGL(k_scatter, dim3(nblocks), dim3(kSortThreads), 0, s, c->keys[src],
+                           (identity && pass == 0) ? (const uint32_t *)nullptr : c->idx[src], c->keys[1 - src],
+                           c->idx[1 - src], np, shift, nblocks, c->hist_scan);
+        c->stats[0] += 5;
+        src = 1 - src;
+    }
+    return src;
 }
 
 hipError_t launch_sort(Ctx *c, const SortArgs &a)
@@ -228,33 +284,28 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
         c->stats[0]++;
         return hipGetLastError();
     }
-    const int per_tile = a.key_mode == PL_KEY_TILE_CELL ? a.tile[0] * a.tile[1] * a.tile[2] : 1;
-    const uint64_t maxkey = (uint64_t)a.ntiles * per_tile - 1;
-    int bits = 1;
-    while (bits < 32 && (maxkey >> bits) != 0) ++bits;
-    const int npass = (bits + 7) / 8;
+    const int per_tile_cells = a.tile[0] * a.tile[1] * a.tile[2];
     const int grid_e = std::min((a.np + 255) / 256, 16 * c->num_cu);
-
-    hipLaunchKernelGGL(k_keys, dim3(grid_e), dim3(256), 0, s, a, c->keys[0]);
-    c->stats[0]++;
-    const int nblocks = (a.np + kPerBlock - 1) / kPerBlock;
-    const long m = 256L * nblocks;
-    const long seg = (m + kScanBlocks - 1) / kScanBlocks;
-    const int nparts = (int)((m + seg - 1) / seg);
-    uint32_t *part = c->hist_scan + m;
-    int src = 0;
-    for (int pass = 0; pass < npass; ++pass) {
-        int shift = 8 * pass;
-        hipLaunchKernelGGL(k_hist, dim3(nblocks), dim3(kSortThreads), 0, s, c->keys[src], a.np, shift, nblocks,
-                           c->hist);
-        hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(256), 0, s, c->hist, m, seg, part);
-        hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanBlocks), 0, s, part, nparts);
-        hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(256), 0, s, c->hist, m, seg, part, c->hist_scan);
-        hipLaunchKernelGGL(k_scatter, dim3(nblocks), dim3(kSortThreads), 0, s, c->keys[src],
-                           pass == 0 ? (const uint32_t *)nullptr : c->idx[src], c->keys[1 - src], c->idx[1 - src],
-                           a.np, shift, nblocks, c->hist_scan);
-        c->stats[0] += 5;
-        src = 1 - src;
+    int src, shift = 0, div = 1;
+    if (a.key_mode == PL_KEY_TILE_RANK) {
+        // phase 1: stable sort by (tile, cell); phase 2: stable sort by
+        // (tile, rank in cell, cell) on top of it
+        SortArgs b = a;
+        b.key_mode = PL_KEY_TILE_CELL;
+        hipLaunchKernelGGL(k_keys, dim3(grid_e), dim3(256), 0, s, b, c->keys[0]);
+        src = radix_passes(c, a.np, 0, true, bits_for((uint64_t)a.ntiles * per_tile_cells));
+        const int cb = bits_for((uint64_t)per_tile_cells), tb = bits_for((uint64_t)a.ntiles);
+        const int rb = std::min(10, 32 - tb - cb);
+        hipLaunchKernelGGL(k_cell_start, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, c->cell_start);
+        hipLaunchKernelGGL(k_rank_keys, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, c->cell_start, cb, rb);
+        src = radix_passes(c, a.np, src, false, tb + rb + cb);
+        shift = rb + cb;
+        c->stats[0] += 3;
+    } else {
+        hipLaunchKernelGGL(k_keys, dim3(grid_e), dim3(256), 0, s, a, c->keys[0]);
+        div = a.key_mode == PL_KEY_TILE_CELL ? per_tile_cells : 1;
+        src = radix_passes(c, a.np, 0, true, bits_for((uint64_t)a.ntiles * div));
+        c->stats[0]++;
     }
     const uint32_t *perm = c->idx[src];
     for (int k = 0; k < a.narrays; ++k) {
@@ -264,7 +315,7 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
             hipLaunchKernelGGL(k_permute<4>, dim3(grid_e), dim3(256), 0, s, perm, a.np, a.src[k], a.dst[k]);
         c->stats[0]++;
     }
-    hipLaunchKernelGGL(k_tile_start, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, per_tile, a.ntiles,
+    hipLaunchKernelGGL(k_tile_start, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, shift, div, a.ntiles,
                        a.tile_start);
     c->stats[0]++;
     return hipGetLastError();

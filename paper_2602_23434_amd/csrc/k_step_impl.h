@@ -1,4 +1,5 @@
-// Gather -> push -> deposit kernels for gfx950.
+// Gather -> push -> deposit kernels for gfx950 (template; instantiated per
+// precision in k_step_f32.hip and k_step_f64.hip).
 //
 // One templated body serves both algorithms:
 //  * PLAIN: one thread per particle; fields are read from HBM/L2 at the 27
@@ -13,20 +14,17 @@
 // Work units of all items of a call are claimed from one atomic counter by a
 // persistent grid sized to the chip's resident capacity; items are ordered
 // largest first on the host.
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <map>
+#include <vector>
 
 #include "pl_device.h"
 
 namespace pl {
-
-enum StepFlag : unsigned {
-    SF_PUSH = 1u,       // advance particles (else: deposit the current state)
-    SF_DEPOSIT = 2u,    // deposit moments
-    SF_SUMS = 4u,       // particle-side conservation sums
-};
 
 template <int DIM> struct Stencil {
     static constexpr int SY = DIM >= 2 ? 3 : 1;
@@ -63,13 +61,6 @@ __device__ __forceinline__ int find_item(const ItemDesc *items, int nitems, int 
     int it = 0;
     while (it + 1 < nitems && items[it + 1].unit_begin <= g) ++it;
     return it;
-}
-
-template <typename R>
-__device__ __forceinline__ R wave_sum(R v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
 }
 
 // Per-unit constants: read once from the item table into registers when a
@@ -282,7 +273,7 @@ __host__ __device__ inline size_t step_lds_bytes(int prec, int kind, int L, bool
     return f + (size_t)L * nslot * 8 + 16;
 }
 
-template <int PREC, int SHAPE, int DIM, bool TILED>
+template <int PREC, int SHAPE, int DIM, bool TILED, int KIND>
 __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items, int nitems, int total_units,
                                                unsigned *counter, int *errflags, unsigned flags, int lds_bytes)
 {
@@ -331,10 +322,10 @@ __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items
 
         UnitC<PREC> U;
         load_unit<PREC>(I, U, tg.L);
-        const int kind = U.kind;
-        const bool dep_here = do_dep && kind != PL_TRACER && I.nslot > 0;
+        constexpr int kind = KIND;
+        const bool dep_here = KIND != PL_TRACER && do_dep && I.nslot > 0;
         const int nslot = I.nslot;
-        const int nf = kind == PL_LORENTZ ? 6 : 3;
+        constexpr int nf = KIND == PL_LORENTZ ? 6 : 3;
         R *lds_f = reinterpret_cast<R *>(smem_raw);
         size_t foff = do_push ? ((size_t)tg.L * nf * sizeof(R) + 15) & ~(size_t)15 : 0;
         double *lds_d = reinterpret_cast<double *>(smem_raw + foff);
@@ -361,15 +352,16 @@ __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items
 #pragma unroll
         for (int k = 0; k < 8; ++k) ps[k] = 0.0;
 
-        // Tiled: thread t takes the contiguous run [pbeg + t*run, +run) of the
-        // tile's particles.  With particles sorted by cell, the 64 lanes of a
-        // wave then sit in about 64 consecutive cells at every step of the
-        // run, so their LDS reads and adds fall in distinct banks.  Plain: one
-        // particle per thread, grid-strided.
-        const int run = TILED ? (pend - pbeg + (int)blockDim.x - 1) / (int)blockDim.x : 1;
-        const int pfirst = TILED ? pbeg + (int)threadIdx.x * run : pbeg + (int)threadIdx.x;
-        const int plast = TILED ? min(pend, pfirst + run) : pend;
-        const int pstep = TILED ? 1 : (int)blockDim.x;
+        // Default: consecutive lanes take consecutive particles (coalesced
+        // loads and stores; with particles sorted by cell, lanes of one cell
+        // read the same LDS words, which the LDS broadcasts).  With SF_RUNS
+        // thread t takes the contiguous run [pbeg + t*run, +run) instead, so
+        // the lanes of a wave sit in about 64 distinct consecutive cells.
+        const bool runs = TILED && (flags & SF_RUNS);
+        const int run = runs ? (pend - pbeg + (int)blockDim.x - 1) / (int)blockDim.x : 1;
+        const int pfirst = runs ? pbeg + (int)threadIdx.x * run : pbeg + (int)threadIdx.x;
+        const int plast = runs ? min(pend, pfirst + run) : pend;
+        const int pstep = runs ? 1 : (int)blockDim.x;
         for (int p = pfirst; p < plast; p += pstep) {
             Pos<PREC, DIM> pos;
             pos.load(U, p, err);
@@ -386,7 +378,7 @@ __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items
                 int base = 0;
                 bool inl = TILED && in_tile<DIM>(tg, pos.c, base);
                 R v[3];
-                if (kind == PL_LORENTZ) {
+                if constexpr (KIND == PL_LORENTZ) {
                     R EB[6];
                     gather<PREC, DIM, 6>(U, lds_f, tg.L, inl, base, tg.Lx, tg.LxLy, pos.c, wx, wy, wz, EB);
                     R du[3];
@@ -406,7 +398,7 @@ __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items
                         mu[1 + a] = (double)(qw * v[a]);
                         mu[4 + a] = (double)(mw * du[a] * U.inv_dt);
                     }
-                    if (PREC == PL_F64) {
+                    if constexpr (PREC == PL_F64) {
                         mu[7] = (double)(mw * U.c2 * (gn - go) * U.inv_dt);
                     } else {
                         // c^2 (gamma_new - gamma_old) without the cancellation:
@@ -418,7 +410,7 @@ __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items
 #pragma unroll
                         for (int a = 0; a < 3; ++a) U.fp[a][p] = (R)mu[4 + a];
                     }
-                } else if (kind == PL_DUST) {
+                } else if constexpr (KIND == PL_DUST) {
                     R vg[3];
                     gather<PREC, DIM, 3>(U, lds_f, tg.L, inl, base, tg.Lx, tg.LxLy, pos.c, wx, wy, wz, vg);
                     R du[3];
@@ -465,7 +457,7 @@ __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items
                 for (int a = 0; a < 3; ++a) U.u[a][p] = u[a];
             } else {
                 // deposit of the current state
-                if (kind == PL_LORENTZ) {
+                if constexpr (KIND == PL_LORENTZ) {
                     R g2 = sqrt(fma(fma(u[0], u[0], fma(u[1], u[1], u[2] * u[2])), U.inv_c2, R(1)));
                     R qw = U.q * w;
                     mu[0] = (double)qw;
@@ -495,7 +487,7 @@ __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items
             }
         }
 
-        if (do_sums && kind != PL_TRACER) {
+        if (KIND != PL_TRACER && do_sums) {
             for (int k = 0; k < 8; ++k) {
                 double sw = wave_sum(ps[k]);
                 if ((threadIdx.x & 63) == 0 && sw != 0.0) global_add(I.psum + k, sw);
@@ -535,28 +527,26 @@ __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items
 }
 
 // ---------------------------------------------------------------------------
-// Host launchers
+// Host side: launch one persistent kernel over one group of items of the
+// same species kind.
 // ---------------------------------------------------------------------------
 
 using StepKernel = void (*)(const ItemDesc *, int, int, unsigned *, int *, unsigned, int);
 
-static StepKernel pick(int prec, int shape, int dim, bool tiled)
+template <int PREC>
+static StepKernel pick_kernel(int shape, int dim, bool tiled, int kind)
 {
-#define PL_PICK(P, S, D, T) \
-    if (prec == P && shape == S && dim == D && tiled == T) return k_step<P, S, D, T>;
-    PL_PICK(PL_F64, PL_TSC, 3, false) PL_PICK(PL_F64, PL_TSC, 3, true)
-    PL_PICK(PL_F64, PL_TSC, 2, false) PL_PICK(PL_F64, PL_TSC, 2, true)
-    PL_PICK(PL_F64, PL_CIC, 3, false) PL_PICK(PL_F64, PL_CIC, 3, true)
-    PL_PICK(PL_F64, PL_CIC, 2, false) PL_PICK(PL_F64, PL_CIC, 2, true)
-    PL_PICK(PL_F32_OFFSET, PL_TSC, 3, false) PL_PICK(PL_F32_OFFSET, PL_TSC, 3, true)
-    PL_PICK(PL_F32_OFFSET, PL_TSC, 2, false) PL_PICK(PL_F32_OFFSET, PL_TSC, 2, true)
-    PL_PICK(PL_F32_OFFSET, PL_CIC, 3, false) PL_PICK(PL_F32_OFFSET, PL_CIC, 3, true)
-    PL_PICK(PL_F32_OFFSET, PL_CIC, 2, false) PL_PICK(PL_F32_OFFSET, PL_CIC, 2, true)
+#define PL_PICK(S, D, T, K) \
+    if (shape == S && dim == D && tiled == T && kind == K) return k_step<PREC, S, D, T, K>;
+#define PL_PICK_K(S, D, T) PL_PICK(S, D, T, PL_LORENTZ) PL_PICK(S, D, T, PL_DUST) PL_PICK(S, D, T, PL_TRACER)
+    PL_PICK_K(PL_TSC, 3, false) PL_PICK_K(PL_TSC, 3, true) PL_PICK_K(PL_TSC, 2, false) PL_PICK_K(PL_TSC, 2, true)
+    PL_PICK_K(PL_CIC, 3, false) PL_PICK_K(PL_CIC, 3, true) PL_PICK_K(PL_CIC, 2, false) PL_PICK_K(PL_CIC, 2, true)
+#undef PL_PICK_K
 #undef PL_PICK
     return nullptr;
 }
 
-static int resident_blocks(Ctx *c, StepKernel k, int block, size_t lds)
+static inline int resident_blocks(Ctx *c, StepKernel k, int block, size_t lds)
 {
     static std::map<std::pair<const void *, std::pair<int, size_t>>, int> cache;
     auto key = std::make_pair((const void *)k, std::make_pair(block, lds));
@@ -569,181 +559,29 @@ static int resident_blocks(Ctx *c, StepKernel k, int block, size_t lds)
     return r;
 }
 
-hipError_t launch_step(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc> &host, int nitems,
-                       int total_units, unsigned flags, bool deposit, bool push)
+template <int PREC>
+hipError_t launch_group_impl(Ctx *c, const ItemDesc *table, const ItemDesc *host, int nitems, int total_units,
+                             unsigned sf, bool push, bool deposit, unsigned *counter)
 {
     if (total_units <= 0) return hipSuccess;
     const bool tiled = c->d.algo == PL_ALGO_TILED;
-    StepKernel k = pick(c->d.prec, c->d.shape, c->d.ndim, tiled);
+    const int kind = host[0].kind;
+    StepKernel k = pick_kernel<PREC>(c->d.shape, c->d.ndim, tiled, kind);
     if (!k) return hipErrorInvalidValue;
-    unsigned sf = (push ? SF_PUSH : 0u) | (deposit ? SF_DEPOSIT : 0u) | ((flags & PL_SUMS) ? SF_SUMS : 0u);
     size_t lds = 16;
     if (tiled) {
-        for (const ItemDesc &it : host) {
-            int Lx = it.tile[0] + 2;
-            int Ly = it.tile[1] + 2;
-            int Lz = c->d.ndim >= 3 ? it.tile[2] + 2 : 1;
-            int L = Lx * Ly * Lz;
+        for (int i = 0; i < nitems; ++i) {
+            const ItemDesc &it = host[i];
+            int L = (it.tile[0] + 2) * (it.tile[1] + 2) * (c->d.ndim >= 3 ? it.tile[2] + 2 : 1);
             int ns = (deposit && it.kind != PL_TRACER) ? it.nslot : 0;
-            lds = std::max(lds, step_lds_bytes(c->d.prec, it.kind, L, push, ns));
+            lds = std::max(lds, step_lds_bytes(PREC, it.kind, L, push, ns));
         }
         if (lds > (size_t)c->lds_max) return hipErrorInvalidConfiguration;
     }
     int block = c->block;
     int grid = std::min(total_units, resident_blocks(c, k, block, lds));
-    hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, c->stream, table, nitems, total_units, c->counters,
-                       c->errflags, sf, (int)lds);
-    c->stats[0]++;
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Zeroing, sums, pack / unpack
-// ---------------------------------------------------------------------------
-
-__global__ void k_zero(double *p, long n)
-{
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0.0;
-}
-
-hipError_t launch_zero(Ctx *c, const std::vector<ItemDesc> &host)
-{
-    for (const ItemDesc &it : host) {
-        if (it.kind == PL_TRACER) continue;
-        long cells = (long)it.n[0] * it.n[1] * it.n[2];
-        int grid = (int)std::min<long>((cells + 255) / 256, 8L * c->num_cu);
-        for (int ch = 0; ch < kMaxCh; ++ch) {
-            if (it.slot[ch] < 0) continue;
-            hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, c->stream, it.M[ch], cells);
-            c->stats[0]++;
-        }
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_zero_sums(Ctx *c, double *sums, int n)
-{
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, c->stream, sums, (long)n);
-    c->stats[0]++;
-    return hipGetLastError();
-}
-
-__global__ void k_grid_sum(const double *p, long n, double scale, double *out)
-{
-    double s = 0.0;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) s += p[i];
-    s = wave_sum(s);
-    __shared__ double part[16];
-    int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) part[wv] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += part[k];
-        global_add(out, t * scale);
-    }
-}
-
-hipError_t launch_grid_sums(Ctx *c, const ItemDesc &it, double *out8)
-{
-    long cells = (long)it.n[0] * it.n[1] * it.n[2];
-    double dv = 1.0 / it.inv_dv;
-    int grid = (int)std::min<long>((cells + 255) / 256, 4L * c->num_cu);
-    for (int ch = 0; ch < kMaxCh; ++ch) {
-        if (!it.M[ch]) continue;
-        hipLaunchKernelGGL(k_grid_sum, dim3(grid), dim3(256), 0, c->stream, it.M[ch], cells, dv, out8 + ch);
-        c->stats[0]++;
-    }
-    return hipGetLastError();
-}
-
-template <int PREC>
-__global__ void k_pack(ItemDesc it, int ndim, const double *x0, const double *x1, const double *x2,
-                       const double *u0, const double *u1, const double *u2, int *errflags)
-{
-    const double *xs[3] = {x0, x1, x2};
-    const double *us[3] = {u0, u1, u2};
-    int err = 0;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < it.np; p += gridDim.x * blockDim.x) {
-        int c[3] = {0, 0, 0};
-        double xw[3] = {0.0, 0.0, 0.0};
-        for (int a = 0; a < 3; ++a)
-            if (!isfinite(us[a][p])) err |= ERR_NONFINITE;
-        for (int a = 0; a < ndim; ++a) {
-            double v = xs[a][p];
-            double nn = (double)it.n[a];
-            if (!(v >= 0.0 && v < nn)) {
-                if (!isfinite(v)) { v = 0.0; err |= ERR_NONFINITE; }
-                v = v - nn * floor(v / nn);
-                if (v >= nn || v < 0.0) v = 0.0;
-            }
-            xw[a] = v;
-        }
-        if (PREC == PL_F64) {
-            for (int a = 0; a < ndim; ++a) ((double *)it.x[a])[p] = xw[a];
-            for (int a = 0; a < 3; ++a) ((double *)it.u[a])[p] = us[a][p];
-        } else {
-            for (int a = 0; a < ndim; ++a) {
-                double f = floor(xw[a]);
-                int ci = (int)f;
-                float o = (float)(xw[a] - f - 0.5);
-                if (o >= 0.5f) {
-                    o = -0.5f;
-                    ci = ci + 1 == it.n[a] ? 0 : ci + 1;
-                }
-                c[a] = ci;
-                ((float *)it.x[a])[p] = o;
-            }
-            it.cell[p] = pack_cell(c[0], c[1], c[2]);
-            for (int a = 0; a < 3; ++a) ((float *)it.u[a])[p] = (float)us[a][p];
-        }
-    }
-    if (err) atomicOr(errflags, err);
-}
-
-template <int PREC>
-__global__ void k_unpack(ItemDesc it, int ndim, double *x0, double *x1, double *x2, double *u0, double *u1,
-                         double *u2)
-{
-    double *xs[3] = {x0, x1, x2};
-    double *us[3] = {u0, u1, u2};
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < it.np; p += gridDim.x * blockDim.x) {
-        if (PREC == PL_F64) {
-            for (int a = 0; a < ndim; ++a) xs[a][p] = ((const double *)it.x[a])[p];
-            for (int a = 0; a < 3; ++a) us[a][p] = ((const double *)it.u[a])[p];
-        } else {
-            int c[3];
-            unpack_cell(it.cell[p], c[0], c[1], c[2]);
-            for (int a = 0; a < ndim; ++a) xs[a][p] = (double)c[a] + 0.5 + (double)((const float *)it.x[a])[p];
-            for (int a = 0; a < 3; ++a) us[a][p] = (double)((const float *)it.u[a])[p];
-        }
-    }
-}
-
-hipError_t launch_pack(Ctx *c, const ItemDesc &it, int prec, int ndim, const double *x[3], const double *u[3])
-{
-    if (it.np == 0) return hipSuccess;
-    int grid = std::min((it.np + 255) / 256, 16 * c->num_cu);
-    if (prec == PL_F64)
-        hipLaunchKernelGGL(k_pack<PL_F64>, dim3(grid), dim3(256), 0, c->stream, it, ndim, x[0], x[1], x[2], u[0],
-                           u[1], u[2], c->errflags);
-    else
-        hipLaunchKernelGGL(k_pack<PL_F32_OFFSET>, dim3(grid), dim3(256), 0, c->stream, it, ndim, x[0], x[1], x[2],
-                           u[0], u[1], u[2], c->errflags);
-    c->stats[0]++;
-    return hipGetLastError();
-}
-
-hipError_t launch_unpack(Ctx *c, const ItemDesc &it, int prec, int ndim, double *x[3], double *u[3])
-{
-    if (it.np == 0) return hipSuccess;
-    int grid = std::min((it.np + 255) / 256, 16 * c->num_cu);
-    if (prec == PL_F64)
-        hipLaunchKernelGGL(k_unpack<PL_F64>, dim3(grid), dim3(256), 0, c->stream, it, ndim, x[0], x[1], x[2], u[0],
-                           u[1], u[2]);
-    else
-        hipLaunchKernelGGL(k_unpack<PL_F32_OFFSET>, dim3(grid), dim3(256), 0, c->stream, it, ndim, x[0], x[1], x[2],
-                           u[0], u[1], u[2]);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, c->stream, table, nitems, total_units, counter, c->errflags,
+                       sf, (int)lds);
     c->stats[0]++;
     return hipGetLastError();
 }

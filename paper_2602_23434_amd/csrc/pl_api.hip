@@ -33,7 +33,8 @@ pl_status validate_desc(const pl_init_desc *d)
     if (d->prec != PL_F64 && d->prec != PL_F32_OFFSET) return PL_EINVAL;
     if (d->shape != PL_CIC && d->shape != PL_TSC) return PL_EINVAL;
     if (d->algo != PL_ALGO_PLAIN && d->algo != PL_ALGO_TILED) return PL_EINVAL;
-    if (d->key_mode != PL_KEY_TILE && d->key_mode != PL_KEY_TILE_CELL) return PL_EINVAL;
+    if (d->key_mode != PL_KEY_TILE && d->key_mode != PL_KEY_TILE_CELL && d->key_mode != PL_KEY_TILE_RANK)
+        return PL_EINVAL;
     if (!finite_pos(d->c)) return PL_EINVAL;
     if (d->nboxes < 1 || !d->boxes || d->nspecies < 1 || !d->species) return PL_EINVAL;
     if (d->max_items < 1 || d->max_items > 4096) return PL_EINVAL;
@@ -67,7 +68,7 @@ int divisor_at_most(int n, int want)
     return 1;
 }
 
-void read_tune_cache(const char *path, int &block, int tile[3])
+void read_tune_cache(const char *path, int &block, int tile[3], int &runs)
 {
     if (!path) return;
     FILE *f = fopen(path, "r");
@@ -76,7 +77,10 @@ void read_tune_cache(const char *path, int &block, int tile[3])
     while (fscanf(f, "%63s", key) == 1) {
         if (!strcmp(key, "block")) {
             int v;
-            if (fscanf(f, "%d", &v) == 1 && v >= 64 && v <= 1024 && v % 64 == 0) block = v;
+            if (fscanf(f, "%d", &v) == 1 && v >= 64 && v <= 512 && v % 64 == 0) block = v;
+        } else if (!strcmp(key, "runs")) {
+            int v;
+            if (fscanf(f, "%d", &v) == 1) runs = v != 0;
         } else if (!strcmp(key, "tile")) {
             int a, b, c;
             if (fscanf(f, "%d %d %d", &a, &b, &c) == 3 && a > 0 && b > 0 && c > 0) {
@@ -108,6 +112,7 @@ void free_ctx(Ctx *c)
     }
     (void)hipFree(c->hist);
     (void)hipFree(c->hist_scan);
+    (void)hipFree(c->cell_start);
     for (int k = 0; k < Ctx::kRing; ++k)
         if (c->ring_ev[k]) (void)hipEventDestroy(c->ring_ev[k]);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -232,19 +237,26 @@ pl_status build_table(Ctx *c, const pl_item *items, int nitems, double dt, Mode 
     for (int i = 0; i < nitems; ++i)
         for (int j = i + 1; j < nitems; ++j)
             if (descs[i].np > 0 && descs[j].np > 0 && descs[i].u[0] == descs[j].u[0]) return PL_EINVAL;
+    // grouped by species kind (one launch per kind), largest items first
     std::vector<int> order(nitems);
     for (int i = 0; i < nitems; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return descs[a].np > descs[b].np; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (descs[a].kind != descs[b].kind) return descs[a].kind < descs[b].kind;
+        return descs[a].np > descs[b].np;
+    });
     host.clear();
     total_units = 0;
     const bool tiled = c->d.algo == PL_ALGO_TILED;
     const int chunk = c->block * 4;
+    int group_units = 0;
     for (int k = 0; k < nitems; ++k) {
         ItemDesc D = descs[order[k]];
-        D.unit_begin = total_units;
+        if (k > 0 && D.kind != host.back().kind) group_units = 0;
+        D.unit_begin = group_units;
         D.chunk = chunk;
         D.nunits = tiled ? D.ntiles : (D.np + chunk - 1) / chunk;
         if (D.np == 0) D.nunits = 0;
+        group_units += D.nunits;
         total_units += D.nunits;
         host.push_back(D);
     }
@@ -376,16 +388,33 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d)
     c->stream = (hipStream_t)d->stream;
     c->max_np = d->max_np;
 
-    int tuned_block = 256, tuned_tile[3] = {8, 8, 8};
+    int tuned_block = 256, tuned_tile[3] = {8, 8, 8}, tuned_runs = 0;
     if (d->prec == PL_F64 && d->algo == PL_ALGO_TILED) { tuned_tile[1] = 4; tuned_tile[2] = 4; }
-    read_tune_cache(d->tune_cache, tuned_block, tuned_tile);
+    read_tune_cache(d->tune_cache, tuned_block, tuned_tile, tuned_runs);
     c->block = d->block ? d->block : tuned_block;
+    c->runs = tuned_runs != 0;
     for (auto &b : c->boxes) {
         if (b.tile[0] == 0) {
             for (int a = 0; a < 3; ++a) b.tile[a] = divisor_at_most(b.n[a], tuned_tile[a]);
             if (d->ndim == 2) b.tile[2] = 1;
         }
         c->max_ntiles = std::max(c->max_ntiles, (b.n[0] / b.tile[0]) * (b.n[1] / b.tile[1]) * (b.n[2] / b.tile[2]));
+    }
+    int64_t max_cells = 0;
+    for (const auto &b : c->boxes) {
+        max_cells = std::max<int64_t>(max_cells, (int64_t)b.n[0] * b.n[1] * b.n[2]);
+        if (d->key_mode == PL_KEY_TILE_RANK) {
+            // tile bits + cell-in-tile bits must leave at least 3 bits for the rank
+            int64_t nt = (int64_t)(b.n[0] / b.tile[0]) * (b.n[1] / b.tile[1]) * (b.n[2] / b.tile[2]);
+            int64_t pt = (int64_t)b.tile[0] * b.tile[1] * b.tile[2];
+            int tb = 0, cb = 0;
+            while (((int64_t)1 << tb) < nt) ++tb;
+            while (((int64_t)1 << cb) < pt) ++cb;
+            if (32 - tb - cb < 3) {
+                delete c;
+                return PL_EUNSUPPORTED;
+            }
+        }
     }
 
     if (hipGetDevice(&c->device) != hipSuccess ||
@@ -410,6 +439,8 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d)
     for (int k = 0; ok && k < 2; ++k)
         ok = hipMalloc(&c->keys[k], np * sizeof(uint32_t)) == hipSuccess &&
              hipMalloc(&c->idx[k], np * sizeof(uint32_t)) == hipSuccess;
+    if (ok && d->key_mode == PL_KEY_TILE_RANK)
+        ok = hipMalloc(&c->cell_start, (size_t)max_cells * sizeof(int32_t)) == hipSuccess;
     for (int k = 0; ok && k < Ctx::kGraphs; ++k)
         ok = hipMalloc(&c->graphs[k].table, mi * sizeof(ItemDesc)) == hipSuccess;
     for (int k = 0; ok && k < Ctx::kRing; ++k)

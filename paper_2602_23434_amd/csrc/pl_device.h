@@ -12,6 +12,14 @@ namespace pl {
 template <int PREC> struct RealOf { using T = double; };
 template <> struct RealOf<PL_F32_OFFSET> { using T = float; };
 
+// Sum over the 64 lanes of a wave.
+template <typename R>
+__device__ __forceinline__ R wave_sum(R v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // Hardware float64 atomic add on global memory (no compare-and-swap loop).
 __device__ __forceinline__ void global_add(double *p, double v)
 {

@@ -19,6 +19,14 @@ enum Channel { CH_RHO = 0, CH_J0 = 1, CH_F0 = 4, CH_ENG = 7 };
 // Latched device-side error bits.
 enum ErrBit { ERR_CFL = 1, ERR_NONFINITE = 2 };
 
+// Mode bits of the step kernels.
+enum StepFlag : unsigned {
+    SF_PUSH = 1u,       // advance particles (else: deposit the current state)
+    SF_DEPOSIT = 2u,    // deposit moments
+    SF_SUMS = 4u,       // particle-side conservation sums
+    SF_RUNS = 8u,       // tiled: each thread takes a contiguous run of the tile's particles
+};
+
 // Everything a kernel needs to know about one item of a call.  Built on the
 // host for every call, uploaded into the context's item table.
 struct ItemDesc {
@@ -80,6 +88,7 @@ struct Ctx {
     int num_cu = 0;
     int block = 256;
     int lds_max = 65536;
+    bool runs = false;               // tiled: contiguous per-thread particle runs (tune cache "runs 1")
 
     // device scratch
     ItemDesc *table = nullptr;       // max_items descriptors for non-graph calls
@@ -89,6 +98,7 @@ struct Ctx {
     uint32_t *keys[2] = {nullptr, nullptr};
     uint32_t *idx[2] = {nullptr, nullptr};
     uint32_t *hist = nullptr;        // radix digit counts
+    int32_t *cell_start = nullptr;   // rank-interleaved sort: first sorted position of every cell
     uint32_t *hist_scan = nullptr;
     int64_t hist_cap = 0;
     int64_t max_np = 0;

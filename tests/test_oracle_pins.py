@@ -463,6 +463,38 @@ def test_tile_keys_enumeration(orc):
         assert orc.tile_key(3, n, tile, 1, *c) == expect_full[c]
 
 
+def test_rank_keys_structure(orc):
+    """Rank-interleaved keys: sorting by them keeps each tile contiguous, puts
+    particle ranks (number of earlier particles of the same cell) in
+    non-decreasing order inside a tile, never repeats a cell inside one rank
+    level, and keeps the original order of the particles of one cell."""
+    rng = np.random.default_rng(9)
+    n, tile = (8, 8, 4), (4, 4, 2)
+    cells = np.stack([rng.integers(0, n[d], 3000) for d in range(3)])
+    keys, rb = orc.rank_keys(3, n, tile, cells)
+    assert rb == 10
+    perm = orc.stable_sort_perm(keys)
+    seen = {}
+    rank = np.zeros(3000, dtype=np.int64)
+    for p in range(3000):
+        c = tuple(cells[:, p])
+        rank[p] = seen.get(c, 0)
+        seen[c] = rank[p] + 1
+    tiles = np.array([orc.tile_key(3, n, tile, 0, *cells[:, p]) for p in range(3000)])
+    ts, rs = tiles[perm], rank[perm]
+    assert (np.diff(ts) >= 0).all()
+    for t in np.unique(ts):
+        sel = perm[ts == t]
+        r = rank[sel]
+        assert (np.diff(r) >= 0).all()
+        for level in np.unique(r):
+            cl = [tuple(cells[:, p]) for p in sel[r == level]]
+            assert len(cl) == len(set(cl))
+    for c in list(seen)[:50]:
+        pos = [i for i, p in enumerate(perm) if tuple(cells[:, p]) == c]
+        assert [perm[i] for i in pos] == sorted(perm[i] for i in pos)
+
+
 def test_split_position_edges(orc):
     """Compact positions: cell = floor(x); an offset that rounds to +1/2 in
     single precision moves the particle to the next cell at -1/2."""

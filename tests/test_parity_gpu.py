@@ -165,7 +165,7 @@ def test_turbulent_f32_error_table(mods):
 # ---------------------------------------------------------------- sort
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("key_mode", [0, 1])
+@pytest.mark.parametrize("key_mode", [0, 1, 2])
 def test_sort_bitexact(mods, prec, key_mode):
     oracle, driver, inputs, B = mods
     say(f"[parity] sort {prec} key_mode {key_mode}")
@@ -177,17 +177,24 @@ def test_sort_bitexact(mods, prec, key_mode):
         assert run.sync() == B.PL_OK
         raw = run.raw(0)
         x = wl.items[0].particles.x
+        bx = wl.boxes[0].n
         if p == B.PL_F64:
-            keys = oracle.keys_from_positions(3, wl.boxes[0].n, tile, key_mode, x)
+            cells = oracle.cells_of_positions(3, bx, x)
         else:
-            cells, _ = oracle.split_positions(3, wl.boxes[0].n, x)
-            keys = np.array([oracle.tile_key(3, wl.boxes[0].n, tile, key_mode, *cells[:, q])
-                             for q in range(npart)], dtype=np.uint32)
+            cells, _ = oracle.split_positions(3, bx, x)
+        if key_mode == 2:
+            keys, rb = oracle.rank_keys(3, bx, tile, cells)
+        else:
+            keys = np.array([oracle.tile_key(3, bx, tile, key_mode, *cells[:, q]) for q in range(npart)],
+                            dtype=np.uint32)
         perm = oracle.stable_sort_perm(keys)
         assert np.array_equal(raw["id"].astype(np.int64), perm)
-        per_tile = tile[0] * tile[1] * tile[2] if key_mode == 1 else 1
         ntiles = (n // tile[0]) * (n // tile[1]) * (n // tile[2])
-        tkeys = keys[perm] // per_tile
+        per_tile = tile[0] * tile[1] * tile[2]
+        if key_mode == 2:
+            tkeys = keys[perm] >> (rb + int(per_tile - 1).bit_length())
+        else:
+            tkeys = keys[perm] // (per_tile if key_mode == 1 else 1)
         expect = np.searchsorted(tkeys, np.arange(ntiles + 1), side="left")
         assert np.array_equal(raw["tile_start"][: ntiles + 1], expect)
         # every array moved with the permutation
@@ -208,11 +215,11 @@ def test_sort_invariance(mods):
         if prec == B.PL_F64:
             configs = [(B.PL_ALGO_PLAIN, None, 0, 0), (B.PL_ALGO_TILED, (8, 4, 4), 0, 0),
                        (B.PL_ALGO_TILED, (4, 4, 8), 1, 2), (B.PL_ALGO_TILED, (8, 8, 2), 0, 1),
-                       (B.PL_ALGO_TILED, (8, 8, 4), 1, 3)]
+                       (B.PL_ALGO_TILED, (8, 8, 4), 2, 3)]
         else:
             configs = [(B.PL_ALGO_PLAIN, None, 0, 0), (B.PL_ALGO_TILED, (8, 8, 8), 0, 0),
                        (B.PL_ALGO_TILED, (4, 8, 16), 1, 2), (B.PL_ALGO_TILED, (16, 8, 2), 0, 1),
-                       (B.PL_ALGO_TILED, (8, 8, 8), 1, 3)]
+                       (B.PL_ALGO_TILED, (8, 8, 8), 2, 3)]
         for algo, tile, km, every in configs:
             run, st = _run_gpu(driver, wl, wl.steps, algo == B.PL_ALGO_TILED, sort_every=every, prec=prec,
                                algo=algo, tile=tile, key_mode=km)
