@@ -26,8 +26,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL = "k_step"            # the dominant kernel: fused gather -> push -> deposit
-STEP_SRC = os.path.join(ROOT, "paper_2602_23434_amd", "csrc", "k_step.hip")
+# the dominant kernel: fused gather -> push -> deposit, float32 form, TSC, 3D,
+# tiled, charged particles
+KERNEL = "pl::k_step<1, 2, 3, true, 0>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_f32_tiled_turbulent128_traffic.json")
 
 
@@ -50,7 +51,7 @@ def algorithmic_bytes(prec, npart, cells, weights=True, fields=6, channels=7):
 
 def src_digest():
     h = hashlib.sha256()
-    for f in ("k_step.hip", "pl_device.h", "pl_internal.h"):
+    for f in ("k_step_impl.h", "k_step_f32.hip", "pl_device.h", "pl_internal.h"):
         with open(os.path.join(ROOT, "paper_2602_23434_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

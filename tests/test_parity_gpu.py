@@ -408,3 +408,52 @@ def test_invalid_items_rejected(mods):
     assert B.pl_part_gather_push(run.ctx, items, 0.05, B.PL_FUSE_DEPOSIT | B.PL_ZERO_FIRST, check=False) == B.PL_OK
     assert run.sync() == B.PL_OK
     run.close()
+
+
+# ---------------------------------------------------------------- full size, bench configuration
+
+@pytest.mark.parametrize("path", ["f32_tiled", "f64_plain"])
+def test_fullsize_sampled(mods, path):
+    """128^3 turbulent box, 2^24 particles, 20 steps, in the launch
+    configuration the benchmark times.  The oracle advances a sample of 2048
+    particles (a particle's update reads only the fields) and they are compared
+    per id; the deposit is checked through conservation: total charge equals
+    the particle count exactly, and the grid sums of J and F equal the
+    particle-side sums."""
+    oracle, driver, inputs, B = mods
+    from paper_2602_23434_amd import benchcfg as BC
+    say(f"[parity] full size 128^3, 2^24 particles, 20 steps, {path} (bench configuration)")
+    wl = inputs.turbulent_box(n=BC.TURB_N, npart=BC.TURB_NP, steps=20)
+    cfg = BC.F32_TILED if path == "f32_tiled" else BC.F64_PLAIN
+    run = driver.Run(wl, **cfg)
+    if cfg["algo"] == B.PL_ALGO_TILED:
+        run.sort()
+    for s in range(wl.steps):
+        fl = BC.STEP_FLAGS | (B.PL_SUMS if s == wl.steps - 1 else 0)
+        run.step(flags=fl)
+    assert run.sync() == B.PL_OK
+    gx, gu, gid, _ = run.state(0)
+    sums = run.sums()[0]
+    run.close()
+    rng = np.random.default_rng(11)
+    sample = np.sort(rng.choice(BC.TURB_NP, 2048, replace=False))
+    it = wl.items[0].particles
+    x = np.ascontiguousarray(it.x[:, sample])
+    u = np.ascontiguousarray(it.u[:, sample])
+    w = np.ascontiguousarray(it.w[sample])
+    box = wl.boxes[0]
+    for _ in range(wl.steps):
+        oracle.step(3, box.n, oracle.TSC, (oracle.LORENTZ, 1.0, 1.0, 0.0), x, u, w, box.fields, wl.dt)
+    order = np.argsort(gid)
+    gxs, gus = gx[:, order][:, sample], gu[:, order][:, sample]
+    dx = np.abs(_cmp.min_image(gxs - x, 128)).max()
+    du = (np.sqrt(((gus - u) ** 2).sum(axis=0)) / np.maximum(np.sqrt((u * u).sum(axis=0)), 0.05)).max()
+    say(f"  sampled max |dx| {dx:.3e} cells, max |du|/max(|u|,sigma) {du:.3e}")
+    if path == "f64_plain":
+        assert dx <= X_TOL and du <= U_TOL
+    else:
+        assert dx <= 2e-5 and du <= 2e-5
+    tol = 1e-12 if path == "f64_plain" else 1e-6
+    assert abs(sums[0] - BC.TURB_NP) <= tol * BC.TURB_NP
+    for ch in range(1, 7):
+        assert abs(sums[ch] - sums[8 + ch]) <= tol * max(abs(sums[8 + ch]), 1e-3 * BC.TURB_NP * 0.05), ch
