@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # the dominant kernel: fused gather -> push -> deposit, float32 form, TSC, 3D,
 # tiled, charged particles
-KERNEL = "pl::k_step<1, 2, 3, true, 0>"
+KERNEL = "pl::k_step<1, 2, 3, true, 0, 1, 1>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_f32_tiled_turbulent128_traffic.json")
 
 

@@ -76,6 +76,10 @@ typedef int pl_status;
 
 #define PL_ALGO_PLAIN 0    /* one thread per particle, fields and deposits straight from/to HBM */
 #define PL_ALGO_TILED 1    /* per-tile LDS field stage and LDS deposit (needs pl_part_sort) */
+#define PL_ALGO_SPLIT 2    /* tiled push kernel, then a cell-owner deposit kernel in which each lane
+                              sums one channel of one cell over the cell's particles in registers
+                              (needs PL_KEY_TILE_CELL, p.cell_start, and p.fp for the force channel;
+                              no energy channel) */
 
 #define PL_KEY_TILE       0  /* sort by tile */
 #define PL_KEY_TILE_CELL  1  /* sort by tile, then by cell inside the tile (x fastest) */
@@ -109,7 +113,7 @@ typedef struct {
     int ndim;                        /* 2 or 3, for every box of the context */
     int prec;                        /* PL_F64 or PL_F32_OFFSET */
     int shape;                       /* PL_CIC or PL_TSC */
-    int algo;                        /* PL_ALGO_PLAIN or PL_ALGO_TILED */
+    int algo;                        /* PL_ALGO_PLAIN, PL_ALGO_TILED or PL_ALGO_SPLIT */
     int key_mode;                    /* PL_KEY_TILE, PL_KEY_TILE_CELL or PL_KEY_TILE_RANK */
     double c;                        /* speed of light in code units (> 0) */
     int nboxes;
@@ -139,7 +143,10 @@ typedef struct {
     uint64_t *id[2];        /* nullable: particle ids, carried through the sort */
     void *fp[3];            /* nullable: per-particle force m w du/dt, written by gather_push, read by deposit */
     int32_t *tile_start;    /* ntiles+1 first-particle offsets per tile, written by pl_part_sort;
-                               required by PL_ALGO_TILED */
+                               required by PL_ALGO_TILED and PL_ALGO_SPLIT */
+    int32_t *cell_start;    /* nullable: ncells+1 first-particle offsets per cell in sorted order
+                               (cells numbered tile * cells_per_tile + cell in tile), written by
+                               pl_part_sort with PL_KEY_TILE_CELL; required by PL_ALGO_SPLIT */
 } pl_particles;
 
 typedef struct {

@@ -125,6 +125,17 @@ __device__ __forceinline__ void load_unit(const ItemDesc &I, UnitC<PREC> &U, int
     }
 }
 
+// Compile-time channel -> LDS slot maps for the common channel sets (CHS):
+// 0 runtime (UnitC::soff), 1 charged rho, J, F (slots 0..6), 2 dust rho, F
+// (slots 0..3).
+__host__ __device__ constexpr int chs_slot(int CHS, int ch)
+{
+    return CHS == 1 ? (ch < 7 ? ch : -1) : CHS == 2 ? (ch == 0 ? 0 : (ch >= 4 && ch <= 6 ? ch - 3 : -1)) : -1;
+}
+
+// Compile-time tile shapes (TS): 0 runtime, 1 = 8x8x8, 2 = 8x8x4.
+__host__ __device__ constexpr int ts_dim(int TS, int a) { return TS == 1 ? 8 : TS == 2 ? (a < 2 ? 8 : 4) : 0; }
+
 // Tile geometry of one work unit in the LDS (one-cell halo on every side).
 struct TileGeo {
     int lo[3];
@@ -198,9 +209,9 @@ __device__ __forceinline__ void gather(const UnitC<PREC> &U, const typename Real
 // Deposit mu[ch] * W into the float64 LDS tile (or straight into the grids
 // when the stencil leaves the tile).  LDS float64 adds are used because on
 // gfx950 they run about ten times faster than float32 LDS atomic adds.
-template <int PREC, int DIM>
+template <int PREC, int DIM, int CHS>
 __device__ __forceinline__ void deposit(const UnitC<PREC> &U, double *lds_d, bool use_lds, int base, int Lx,
-                                        int LxLy, const int c[3], const typename RealOf<PREC>::T wx[3],
+                                        int LxLy, int L, const int c[3], const typename RealOf<PREC>::T wx[3],
                                         const typename RealOf<PREC>::T wy[3], const typename RealOf<PREC>::T wz[3],
                                         const double mu[kMaxCh])
 {
@@ -218,10 +229,17 @@ __device__ __forceinline__ void deposit(const UnitC<PREC> &U, double *lds_d, boo
                     double w = (double)(wyz * wx[i]);
 #pragma unroll
                     for (int ch = 0; ch < kMaxCh; ++ch) {
-                        int so = U.soff[ch];
-                        if (so >= 0)
-                            __hip_atomic_fetch_add(lds_d + so + row + i, w * mu[ch], __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                        if constexpr (CHS != 0) {
+                            const int sl = chs_slot(CHS, ch);
+                            if (sl >= 0)
+                                __hip_atomic_fetch_add(lds_d + sl * L + row + i, w * mu[ch], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                        } else {
+                            int so = U.soff[ch];
+                            if (so >= 0)
+                                __hip_atomic_fetch_add(lds_d + so + row + i, w * mu[ch], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
                     }
                 }
             }
@@ -241,8 +259,10 @@ __device__ __forceinline__ void deposit(const UnitC<PREC> &U, double *lds_d, boo
                     double w = (double)(wyz * wx[i]) * U.inv_dv;
                     long g = row + ix[i];
 #pragma unroll
-                    for (int ch = 0; ch < kMaxCh; ++ch)
-                        if (U.soff[ch] >= 0) global_add(U.M[ch] + g, w * mu[ch]);
+                    for (int ch = 0; ch < kMaxCh; ++ch) {
+                        bool on = CHS != 0 ? chs_slot(CHS, ch) >= 0 : U.soff[ch] >= 0;
+                        if (on) global_add(U.M[ch] + g, w * mu[ch]);
+                    }
                 }
             }
     }
@@ -273,8 +293,8 @@ __host__ __device__ inline size_t step_lds_bytes(int prec, int kind, int L, bool
     return f + (size_t)L * nslot * 8 + 16;
 }
 
-template <int PREC, int SHAPE, int DIM, bool TILED, int KIND>
-__global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items, int nitems, int total_units,
+template <int PREC, int SHAPE, int DIM, bool TILED, int KIND, int TS, int CHS>
+__global__ __launch_bounds__(512, (TILED && PREC == PL_F32_OFFSET && KIND != PL_TRACER) ? 4 : 1) void k_step(const ItemDesc *__restrict__ items, int nitems, int total_units,
                                                unsigned *counter, int *errflags, unsigned flags, int lds_bytes)
 {
     using R = typename RealOf<PREC>::T;
@@ -299,9 +319,9 @@ __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items
             int tx = t % I.ntile[0];
             int ty = (t / I.ntile[0]) % I.ntile[1];
             int tz = t / (I.ntile[0] * I.ntile[1]);
-            tg.T[0] = I.tile[0];
-            tg.T[1] = I.tile[1];
-            tg.T[2] = I.tile[2];
+            tg.T[0] = TS ? ts_dim(TS, 0) : I.tile[0];
+            tg.T[1] = TS ? ts_dim(TS, 1) : I.tile[1];
+            tg.T[2] = TS ? ts_dim(TS, 2) : I.tile[2];
             tg.lo[0] = tx * tg.T[0];
             tg.lo[1] = ty * tg.T[1];
             tg.lo[2] = tz * tg.T[2];
@@ -483,7 +503,7 @@ __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items
                 stencil_weights<PREC, SHAPE, DIM>(dn, wx, wy, wz);
                 int base = 0;
                 bool inl = TILED && in_tile<DIM>(tg, pos.c, base);
-                deposit<PREC, DIM>(U, lds_d, inl, base, tg.Lx, tg.LxLy, pos.c, wx, wy, wz, mu);
+                deposit<PREC, DIM, CHS>(U, lds_d, inl, base, tg.Lx, tg.LxLy, tg.L, pos.c, wx, wy, wz, mu);
             }
         }
 
@@ -507,7 +527,7 @@ __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items
                 long gc = gx + (long)U.n[0] * (gy + (long)U.n[1] * gz);
 #pragma unroll
                 for (int ch = 0; ch < kMaxCh; ++ch) {
-                    int so = U.soff[ch];
+                    int so = CHS != 0 ? (chs_slot(CHS, ch) >= 0 ? chs_slot(CHS, ch) * tg.L : -1) : U.soff[ch];
                     if (so < 0) continue;
                     double val = lds_d[so + e];
                     if (val != 0.0) global_add(U.M[ch] + gc, val * U.inv_dv);
@@ -533,16 +553,23 @@ __global__ __launch_bounds__(512) void k_step(const ItemDesc *__restrict__ items
 
 using StepKernel = void (*)(const ItemDesc *, int, int, unsigned *, int *, unsigned, int);
 
+// Kernel variants: the 3D TSC tiled kernels also come with a compile-time tile
+// shape (TS) and channel set (CHS) so LDS addresses become immediate offsets.
 template <int PREC>
-static StepKernel pick_kernel(int shape, int dim, bool tiled, int kind)
+static StepKernel pick_kernel(int shape, int dim, bool tiled, int kind, int ts, int chs)
 {
-#define PL_PICK(S, D, T, K) \
-    if (shape == S && dim == D && tiled == T && kind == K) return k_step<PREC, S, D, T, K>;
-#define PL_PICK_K(S, D, T) PL_PICK(S, D, T, PL_LORENTZ) PL_PICK(S, D, T, PL_DUST) PL_PICK(S, D, T, PL_TRACER)
-    PL_PICK_K(PL_TSC, 3, false) PL_PICK_K(PL_TSC, 3, true) PL_PICK_K(PL_TSC, 2, false) PL_PICK_K(PL_TSC, 2, true)
-    PL_PICK_K(PL_CIC, 3, false) PL_PICK_K(PL_CIC, 3, true) PL_PICK_K(PL_CIC, 2, false) PL_PICK_K(PL_CIC, 2, true)
-#undef PL_PICK_K
-#undef PL_PICK
+#define PL_K(S, D, T, K, TS_, CHS_) \
+    if (shape == S && dim == D && tiled == T && kind == K && ts == TS_ && chs == CHS_) \
+        return k_step<PREC, S, D, T, K, TS_, CHS_>;
+#define PL_KIND_ALL(S, D, T) PL_K(S, D, T, PL_LORENTZ, 0, 0) PL_K(S, D, T, PL_DUST, 0, 0) PL_K(S, D, T, PL_TRACER, 0, 0)
+#define PL_FAST(TS_) PL_K(PL_TSC, 3, true, PL_LORENTZ, TS_, 0) PL_K(PL_TSC, 3, true, PL_LORENTZ, TS_, 1) \
+    PL_K(PL_TSC, 3, true, PL_DUST, TS_, 0) PL_K(PL_TSC, 3, true, PL_DUST, TS_, 2) PL_K(PL_TSC, 3, true, PL_TRACER, TS_, 0)
+    PL_KIND_ALL(PL_TSC, 3, false) PL_KIND_ALL(PL_TSC, 2, false) PL_KIND_ALL(PL_TSC, 2, true)
+    PL_KIND_ALL(PL_CIC, 3, false) PL_KIND_ALL(PL_CIC, 3, true) PL_KIND_ALL(PL_CIC, 2, false) PL_KIND_ALL(PL_CIC, 2, true)
+    PL_FAST(0) PL_FAST(1) PL_FAST(2)
+#undef PL_FAST
+#undef PL_KIND_ALL
+#undef PL_K
     return nullptr;
 }
 
@@ -566,7 +593,22 @@ hipError_t launch_group_impl(Ctx *c, const ItemDesc *table, const ItemDesc *host
     if (total_units <= 0) return hipSuccess;
     const bool tiled = c->d.algo == PL_ALGO_TILED;
     const int kind = host[0].kind;
-    StepKernel k = pick_kernel<PREC>(c->d.shape, c->d.ndim, tiled, kind);
+    // compile-time tile shape and channel set when every item of the group allows them
+    int ts = 0, chs = 0;
+    if (tiled && c->d.shape == PL_TSC && c->d.ndim == 3) {
+        for (int cand = 1; cand <= 2 && ts == 0; ++cand) {
+            bool all = true;
+            for (int i = 0; i < nitems; ++i)
+                for (int a = 0; a < 3; ++a) all = all && host[i].tile[a] == ts_dim(cand, a);
+            if (all) ts = cand;
+        }
+        int want = kind == PL_LORENTZ ? 1 : kind == PL_DUST ? 2 : 0;
+        bool all = want != 0 && deposit;
+        for (int i = 0; i < nitems && all; ++i)
+            for (int ch = 0; ch < kMaxCh; ++ch) all = all && host[i].slot[ch] == chs_slot(want, ch);
+        chs = all ? want : 0;
+    }
+    StepKernel k = pick_kernel<PREC>(c->d.shape, c->d.ndim, tiled, kind, ts, chs);
     if (!k) return hipErrorInvalidValue;
     size_t lds = 16;
     if (tiled) {

@@ -57,6 +57,7 @@ int main(void) {
   O(pl_init_desc, block) O(pl_init_desc, stream) O(pl_init_desc, tune_cache)
   S(pl_particles) O(pl_particles, cur) O(pl_particles, cell) O(pl_particles, x) O(pl_particles, u)
   O(pl_particles, w) O(pl_particles, id) O(pl_particles, fp) O(pl_particles, tile_start)
+  O(pl_particles, cell_start)
   S(pl_fields) O(pl_fields, B) O(pl_fields, vg)
   S(pl_moments) O(pl_moments, J) O(pl_moments, F) O(pl_moments, eng)
   S(pl_item) O(pl_item, p) O(pl_item, f) O(pl_item, m)
@@ -109,7 +110,7 @@ def _desc(**kw):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(ndim=4), dict(prec=7), dict(shape=0), dict(algo=3), dict(key_mode=5), dict(c=0.0),
+    dict(ndim=4), dict(prec=7), dict(shape=0), dict(algo=5), dict(key_mode=5), dict(c=0.0),
     dict(c=float("inf")), dict(max_items=0), dict(max_np=-1), dict(max_np=1 << 31), dict(block=100),
     dict(block=1024), dict(n=(8, 8, 2000)), dict(n=(0, 8, 8)), dict(tile=(3, 4, 4)), dict(tile=(0, 4, 4)),
     dict(dx=(1.0, -1.0, 1.0)), dict(kind=9), dict(m=0.0), dict(kind=B.PL_DUST, t_stop=0.0),
