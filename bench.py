@@ -4,12 +4,15 @@ Workload: 128^3 periodic box, turbulent E and B (|k|^-5/3, dB/B0 = 0.5,
 E = -v x B), 2^24 charged particles (q/m = 1, weight 1) placed uniformly with
 Maxwellian velocities (sigma = 0.05 c), TSC weights, dt = 0.05; every step
 gathers E and B, pushes (relativistic Boris) and deposits rho, J and F at the
-new positions.  The headline path is the float32 + cell-offset form with
-LDS-tiled kernels (one initial cell-tile sort as setup, outside the timed
-region); the plain float64 path runs on the same inputs for the speedup.
+new positions.  The headline path is the float32 + cell-offset form with the
+run-based LDS kernel; its tile+cell sort runs inside the timed loop every
+SORT_EVERY steps.  The plain float64 path runs on the same inputs for the
+speedup, and the run-based float64 path and the tiled float32 path beside it.
 
-Prints ONE JSON line.  Inputs are generated on the host, moved to HBM, and
-are resident before the timed region starts.
+Each timed step: zero the moment grids, then one fused gather/push/deposit
+launch (a replayed hipGraph) bracketed by HIP events on the library's stream;
+sorts are bracketed separately.  Prints ONE JSON line.  Inputs are generated
+on the host and are resident in HBM before the timed region starts.
 """
 
 from __future__ import annotations
@@ -18,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -26,10 +30,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# the dominant kernel: fused gather -> push -> deposit, float32 form, TSC, 3D,
-# tiled, charged particles
-KERNEL = "pl::k_step<1, 2, 3, true, 0, 1, 1>"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_f32_tiled_turbulent128_traffic.json")
+# the dominant kernel: run-based gather -> push -> deposit, float32 form, TSC,
+# 3D, charged particles, 512 threads, 8^3 tiles, channels rho + J + F
+KERNEL = "pl::k_runs<1, 2, 3, 0, 512, 1, 1>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_runs_f32_turbulent128_traffic.json")
+DIGEST_FILES = ("k_runs_impl.h", "k_runs_f32.hip", "k_step_impl.h", "pl_device.h", "pl_internal.h")
 
 
 def log(msg):
@@ -51,47 +56,52 @@ def algorithmic_bytes(prec, npart, cells, weights=True, fields=6, channels=7):
 
 def src_digest():
     h = hashlib.sha256()
-    for f in ("k_step_impl.h", "k_step_f32.hip", "pl_device.h", "pl_internal.h"):
+    for f in DIGEST_FILES:
         with open(os.path.join(ROOT, "paper_2602_23434_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def time_path(run, steps, warmup, flags, torch):
-    """Whole-step timing (zeroing + fused kernel) and per-launch timing of the
-    fused kernel alone, both with HIP events on the context's stream."""
-    from paper_2602_23434_amd import binding as B
-    for _ in range(warmup):
+def timed_loop(run, steps, every, graph, torch, B):
+    """`steps` steps with a sort every `every` steps (0: never); returns
+    (loop ms, per-launch kernel ms list, per-sort ms list)."""
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    flags = B.PL_FUSE_DEPOSIT | (B.PL_GRAPH if graph else 0)
+    kpairs, spairs = [], []
+    t0, t1 = ev(), ev()
+    t0.record(run.stream)
+    for s in range(steps):
+        if every and s % every == 0:
+            a, b = ev(), ev()
+            a.record(run.stream)
+            run.sort()
+            b.record(run.stream)
+            spairs.append((a, b))
+        run.zero_moments()
+        a, b = ev(), ev()
+        a.record(run.stream)
         run.step(flags=flags)
-    run.stream.synchronize()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(run.stream)
-    for _ in range(steps):
-        run.step(flags=flags)
-    e1.record(run.stream)
-    e1.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    step_ms = e0.elapsed_time(e1) / steps
+        b.record(run.stream)
+        kpairs.append((a, b))
+    t1.record(run.stream)
+    t1.synchronize()
     st = run.sync()
     if st != B.PL_OK:
         raise RuntimeError(f"device reported status {st}")
-    # the fused kernel alone: one launch per call (no zeroing; deposits add up)
-    kflags = B.PL_FUSE_DEPOSIT
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
-    for k in range(steps):
-        ev[2 * k].record(run.stream)
-        run.step(flags=kflags)
-        ev[2 * k + 1].record(run.stream)
-    ev[-1].synchronize()
-    kern_ms = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(steps)) / steps
-    st = run.sync()
-    if st != B.PL_OK:
-        raise RuntimeError(f"device reported status {st}")
-    return step_ms, kern_ms, wall
+    return (t0.elapsed_time(t1), [a.elapsed_time(b) for a, b in kpairs], [a.elapsed_time(b) for a, b in spairs])
+
+
+def time_path(run, steps, warmup, reps, every, graph, torch, B):
+    if warmup:
+        timed_loop(run, warmup, every, graph, torch, B)
+    loops, kern, sorts = [], [], []
+    for _ in range(reps):
+        ms, k, s = timed_loop(run, steps, every, graph, torch, B)
+        loops.append(ms / steps)
+        kern.extend(k)
+        sorts.extend(s)
+    return {"ms_per_step": statistics.median(loops), "ms_min": min(loops), "ms_max": max(loops),
+            "kernel_ms": sum(kern) / len(kern), "sort_ms": (sum(sorts) / len(sorts)) if sorts else 0.0}
 
 
 def cpu_baseline(wl, target_s=15.0):
@@ -126,10 +136,13 @@ def cpu_baseline(wl, target_s=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=24)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--sort-every", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tiled", action="store_true")
     ap.add_argument("--eager", action="store_true", help="launch steps without hipGraph replay")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -137,7 +150,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2602_23434_amd import benchcfg as BC
@@ -145,7 +157,7 @@ def main():
     from paper_2602_23434_amd import driver, inputs
 
     B.lib()
-    flags = BC.STEP_FLAGS & ~(B.PL_GRAPH if args.eager else 0)
+    every = BC.SORT_EVERY if args.sort_every is None else args.sort_every
     t0 = time.perf_counter()
     wl = inputs.turbulent_box(n=BC.TURB_N, npart=BC.TURB_NP, steps=args.steps)
     log(f"[bench] inputs generated in {time.perf_counter() - t0:.1f} s")
@@ -153,29 +165,35 @@ def main():
     cells = BC.TURB_N ** 3
 
     results = {}
-    paths = [("f32_tiled", BC.F32_TILED)]
+    paths = [("f32_runs", BC.F32_RUNS, every, args.reps)]
+    if not args.no_tiled:
+        paths.append(("f32_tiled", BC.F32_TILED, every, args.reps))
     if not args.no_fp64:
-        paths.append(("f64_plain", BC.F64_PLAIN))
-        paths.append(("f64_tiled", BC.F64_TILED))
-    for name, cfg in paths:
+        paths.append(("f64_plain", BC.F64_PLAIN, 0, 1))
+        paths.append(("f64_runs", BC.F64_RUNS, every, args.reps))
+    for name, cfg, ev_every, reps in paths:
         log(f"[bench] path {name}: setup")
         run = driver.Run(wl, **cfg)
-        if cfg["algo"] == B.PL_ALGO_TILED:
+        if cfg["algo"] != B.PL_ALGO_PLAIN:
             run.sort()
         run.sync()
-        log(f"[bench] path {name}: {args.warmup} warmup + {args.steps} timed steps")
-        step_ms, kern_ms, wall = time_path(run, args.steps, args.warmup, flags, torch)
+        log(f"[bench] path {name}: {args.warmup} warmup + {reps} x {args.steps} timed steps, sort every {ev_every}")
+        r = time_path(run, args.steps, args.warmup, reps, ev_every, not args.eager, torch, B)
         prec = "f32" if cfg["prec"] == B.PL_F32_OFFSET else "f64"
-        abytes = algorithmic_bytes(prec, npart, cells)
-        results[name] = {"ms_per_step": step_ms, "kernel_ms": kern_ms, "updates_per_s": npart / (step_ms * 1e-3),
-                         "alg_bytes": abytes, "wall_s": wall}
-        log(f"[bench] path {name}: {step_ms:.3f} ms/step, kernel {kern_ms:.3f} ms, "
-            f"{npart / (step_ms * 1e-3):.3e} updates/s, {abytes / (kern_ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
+        r["alg_bytes"] = algorithmic_bytes(prec, npart, cells)
+        r["updates_per_s"] = npart / (r["ms_per_step"] * 1e-3)
+        r["stats"] = B.pl_part_stats(run.ctx)
+        results[name] = r
+        log(f"[bench] path {name}: {r['ms_per_step']:.3f} ms/step (min {r['ms_min']:.3f} max {r['ms_max']:.3f}), "
+            f"kernel {r['kernel_ms']:.3f} ms, sort {r['sort_ms']:.3f} ms, {r['updates_per_s']:.3e} updates/s, "
+            f"{r['alg_bytes'] / (r['kernel_ms'] * 1e-3) / 1e9:.0f} GB/s algorithmic, stats {r['stats']}")
         run.close()
         del run
         torch.cuda.empty_cache()
 
-    head = results["f32_tiled"]
+    head = results["f32_runs"]
+    if head["stats"][4] == 0 or head["stats"][5] != 0:
+        raise RuntimeError(f"the run-based kernel did not take the timed steps: stats {head['stats']}")
     achieved = head["alg_bytes"] / (head["kernel_ms"] * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -197,27 +215,28 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "turbulent 128^3 periodic box, 2^24 charged particles (8/cell), TSC, "
-                               "float32 + cell-offset form, LDS-tiled, rank-interleaved cell-tile sort at "
-                               "setup, deposit rho+J+F (inputs of the float64 128^3 configuration)",
+                               "float32 + cell-offset form, run-based LDS kernel, tile+cell sort every "
+                               f"{every} steps inside the timed loop, deposit rho+J+F (inputs of the float64 "
+                               "128^3 configuration)",
                    "grid": [BC.TURB_N] * 3, "particles": npart, "dt": 0.05, "shape": "tsc",
-                   "tile": list(BC.F32_TILED["tile"]), "block": BC.F32_TILED["block"],
-                   "sort_key": "tile+rank+cell",
-                   "graph": not args.eager, "parallelism": "single GPU"},
+                   "tile": list(BC.F32_RUNS["tile"]), "block": BC.F32_RUNS["block"], "sort_key": "tile+cell",
+                   "sort_every": every, "graph": not args.eager, "reps": args.reps,
+                   "ms_per_step_min": head["ms_min"], "ms_per_step_max": head["ms_max"],
+                   "sort_ms": head["sort_ms"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": KERNEL,
                      "kernel_ms": head["kernel_ms"], "alg_bytes_per_launch": head["alg_bytes"]},
     }
+    for name, key in (("f32_tiled", "fp32_tiled"), ("f64_plain", "fp64_plain"), ("f64_runs", "fp64_runs")):
+        if name in results:
+            r = results[name]
+            out[key] = {"value": r["updates_per_s"], "ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
+                        "sort_ms": r["sort_ms"],
+                        "achieved_GBs": r["alg_bytes"] / (r["kernel_ms"] * 1e-3) / 1e9}
     if "f64_plain" in results:
-        f64 = results["f64_plain"]
-        out["fp64_plain"] = {"value": f64["updates_per_s"], "ms_per_step": f64["ms_per_step"],
-                             "kernel_ms": f64["kernel_ms"],
-                             "achieved_GBs": f64["alg_bytes"] / (f64["kernel_ms"] * 1e-3) / 1e9}
-        out["speedup_f32_over_f64_plain"] = head["updates_per_s"] / f64["updates_per_s"]
-    if "f64_tiled" in results:
-        f64t = results["f64_tiled"]
-        out["fp64_tiled"] = {"value": f64t["updates_per_s"], "ms_per_step": f64t["ms_per_step"],
-                             "kernel_ms": f64t["kernel_ms"],
-                             "achieved_GBs": f64t["alg_bytes"] / (f64t["kernel_ms"] * 1e-3) / 1e9}
+        out["speedup_f32_over_f64_plain"] = head["updates_per_s"] / results["f64_plain"]["updates_per_s"]
+    if "f64_runs" in results:
+        out["speedup_f32_over_f64_runs"] = head["updates_per_s"] / results["f64_runs"]["updates_per_s"]
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on host cores)")
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -76,10 +76,12 @@ typedef int pl_status;
 
 #define PL_ALGO_PLAIN 0    /* one thread per particle, fields and deposits straight from/to HBM */
 #define PL_ALGO_TILED 1    /* per-tile LDS field stage and LDS deposit (needs pl_part_sort) */
-#define PL_ALGO_SPLIT 2    /* tiled push kernel, then a cell-owner deposit kernel in which each lane
-                              sums one channel of one cell over the cell's particles in registers
-                              (needs PL_KEY_TILE_CELL, p.cell_start, and p.fp for the force channel;
-                              no energy channel) */
+#define PL_ALGO_RUNS  2    /* per-tile LDS kernel in which each thread advances a run of up to
+                              four particles of one cell: the fields at every stencil point are
+                              read from LDS once for the run and the run's deposits are summed
+                              before each LDS atomic (3D/2D, TSC/CIC, charged and dust species;
+                              tracers and deposit-only calls run the PL_ALGO_TILED kernel).
+                              Needs pl_part_sort with PL_KEY_TILE_CELL, which writes p.runs */
 
 #define PL_KEY_TILE       0  /* sort by tile */
 #define PL_KEY_TILE_CELL  1  /* sort by tile, then by cell inside the tile (x fastest) */
@@ -113,7 +115,7 @@ typedef struct {
     int ndim;                        /* 2 or 3, for every box of the context */
     int prec;                        /* PL_F64 or PL_F32_OFFSET */
     int shape;                       /* PL_CIC or PL_TSC */
-    int algo;                        /* PL_ALGO_PLAIN, PL_ALGO_TILED or PL_ALGO_SPLIT */
+    int algo;                        /* PL_ALGO_PLAIN, PL_ALGO_TILED or PL_ALGO_RUNS */
     int key_mode;                    /* PL_KEY_TILE, PL_KEY_TILE_CELL or PL_KEY_TILE_RANK */
     double c;                        /* speed of light in code units (> 0) */
     int nboxes;
@@ -122,7 +124,9 @@ typedef struct {
     const pl_species_desc *species;  /* host array, copied */
     int max_items;                   /* most items any one call passes (>= 1) */
     int64_t max_np;                  /* most particles in any one item (sizes the sort scratch) */
-    int block;                       /* threads per block of the particle kernels (64..512, multiple of 64); 0 = default */
+    int block;                       /* threads per block of the particle kernels (64..512, multiple of 64;
+                                        with PL_ALGO_RUNS: 512 or 1024 for the run-based kernel);
+                                        0 = default */
     void *stream;                    /* hipStream_t for all work; NULL = the null stream */
     const char *tune_cache;          /* nullable: file written by the autotuner (block, tile) */
 } pl_init_desc;
@@ -143,10 +147,10 @@ typedef struct {
     uint64_t *id[2];        /* nullable: particle ids, carried through the sort */
     void *fp[3];            /* nullable: per-particle force m w du/dt, written by gather_push, read by deposit */
     int32_t *tile_start;    /* ntiles+1 first-particle offsets per tile, written by pl_part_sort;
-                               required by PL_ALGO_TILED and PL_ALGO_SPLIT */
-    int32_t *cell_start;    /* nullable: ncells+1 first-particle offsets per cell in sorted order
-                               (cells numbered tile * cells_per_tile + cell in tile), written by
-                               pl_part_sort with PL_KEY_TILE_CELL; required by PL_ALGO_SPLIT */
+                               required by PL_ALGO_TILED and PL_ALGO_RUNS */
+    int32_t *runs;          /* nullable: n + ntiles run-table entries written by pl_part_sort
+                               with PL_ALGO_RUNS (runs of tile t at [tile_start[t], ...), their
+                               count at runs[n + t]); required by PL_ALGO_RUNS, n < 2^29 */
 } pl_particles;
 
 typedef struct {
@@ -207,6 +211,10 @@ pl_status pl_part_deposit(pl_ctx *ctx, const pl_item *items, int nitems, uint32_
  * w, id) from set cur into set 1-cur, writing p.tile_start, and flipping
  * items[i].p.cur.  Equal keys keep their order (bit-identical to a stable
  * sort).  Requires the 1-cur set for every non-NULL array of set cur.
+ * With PL_ALGO_RUNS it also writes p.runs: the particles of every cell are
+ * cut into runs of up to four consecutive sorted particles, and the runs of a
+ * tile are listed by (index of the run inside its cell, cell in tile), each
+ * entry holding (first particle << 2) | (length - 1).
  */
 pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems);
 
@@ -236,8 +244,11 @@ pl_status pl_part_sync(pl_ctx *ctx);
 /* Change the stream later work is queued on (drops recorded graphs). */
 pl_status pl_part_set_stream(pl_ctx *ctx, void *stream);
 
-/* Number of kernel launches and graph replays queued so far (diagnostics). */
-pl_status pl_part_stats(pl_ctx *ctx, int64_t out[4]);
+/* Diagnostics, counted since pl_part_init: out[0] kernel launches, out[1]
+ * graph replays, out[2] graph recordings, out[3] sorts, out[4] launches of the
+ * run-based kernel, out[5] PL_ALGO_RUNS launch groups that took the tiled
+ * kernel because the run-based kernel's LDS footprint exceeds the device's. */
+pl_status pl_part_stats(pl_ctx *ctx, int64_t out[6]);
 
 /* Free the context and its scratch (synchronises first).  NULL is a no-op. */
 void pl_part_finalize(pl_ctx *ctx);

@@ -15,3 +15,11 @@ F64_PLAIN = dict(prec=B.PL_F64, algo=B.PL_ALGO_PLAIN, key_mode=B.PL_KEY_TILE, ti
                  channels=CHANNELS, eng=False)
 F64_TILED = dict(prec=B.PL_F64, algo=B.PL_ALGO_TILED, key_mode=B.PL_KEY_TILE_RANK, tile=(8, 8, 4), block=512,
                  channels=CHANNELS, eng=False)
+# run-based kernels (tile+cell sort, runs of up to four particles per thread)
+F32_RUNS = dict(prec=B.PL_F32_OFFSET, algo=B.PL_ALGO_RUNS, key_mode=B.PL_KEY_TILE_CELL, tile=(8, 8, 8), block=512,
+                channels=CHANNELS, eng=False)
+F64_RUNS = dict(prec=B.PL_F64, algo=B.PL_ALGO_RUNS, key_mode=B.PL_KEY_TILE_CELL, tile=(8, 8, 4), block=512,
+                channels=CHANNELS, eng=False)
+# steps between sorts inside the timed loop (the autotuner's cadence choice
+# for this workload)
+SORT_EVERY = 8

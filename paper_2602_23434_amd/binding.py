@@ -17,7 +17,7 @@ PL_OK, PL_EINVAL, PL_ENOMEM, PL_EHIP, PL_EUNSUPPORTED, PL_ECFL, PL_ENONFINITE = 
 PL_F64, PL_F32_OFFSET = 0, 1
 PL_CIC, PL_TSC = 1, 2
 PL_LORENTZ, PL_DUST, PL_TRACER = 0, 1, 2
-PL_ALGO_PLAIN, PL_ALGO_TILED, PL_ALGO_SPLIT = 0, 1, 2
+PL_ALGO_PLAIN, PL_ALGO_TILED, PL_ALGO_RUNS = 0, 1, 2
 PL_KEY_TILE, PL_KEY_TILE_CELL, PL_KEY_TILE_RANK = 0, 1, 2
 PL_FUSE_DEPOSIT, PL_ZERO_FIRST, PL_GRAPH, PL_SUMS = 1, 2, 4, 8
 
@@ -48,7 +48,7 @@ class pl_init_desc(C.Structure):
 class pl_particles(C.Structure):
     _fields_ = [("n", C.c_int64), ("cur", C.c_int), ("cell", _vp * 2), ("x", (_vp * 3) * 2),
                 ("u", (_vp * 3) * 2), ("w", _vp * 2), ("id", _vp * 2), ("fp", _vp * 3), ("tile_start", _vp),
-                ("cell_start", _vp)]
+                ("runs", _vp)]
 
 
 class pl_fields(C.Structure):
@@ -176,7 +176,7 @@ def pl_part_set_stream(ctx, stream):
 
 
 def pl_part_stats(ctx):
-    out = (C.c_int64 * 4)()
+    out = (C.c_int64 * 6)()
     _check(lib().pl_part_stats(ctx, out), "pl_part_stats")
     return list(out)
 

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpl.so")
-SOURCES = ["pl_api.hip", "k_util.hip", "k_step_f32.hip", "k_step_f64.hip", "k_sort.hip"]
+SOURCES = ["pl_api.hip", "k_util.hip", "k_step_f32.hip", "k_step_f64.hip", "k_runs_f32.hip", "k_runs_f64.hip",
+           "k_sort.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,765 @@
+// Run-based gather -> push -> deposit kernel for gfx950 (template;
+// instantiated per precision in k_runs_f32.hip and k_runs_f64.hip).
+//
+// Work unit: one (item, cell tile).  The tile+cell sort cuts the particles of
+// every cell into runs of up to kRunLen consecutive particles and lists the
+// runs of a tile by (index of the run inside its cell, cell), so the threads
+// of a wave hold runs of distinct neighbouring cells.  A thread advances its
+// run in register batches of KR particles that share one cell:
+//  * every stencil point's fields are read from LDS once per batch (the
+//    components of a cell are interleaved, so one point is one or three
+//    16-byte reads) and interpolated to all particles of the batch;
+//  * after the push, the batch's deposits are summed per stencil point and
+//    channel before one float64 LDS atomic, cutting LDS atomics by the run
+//    length;
+//  * the LDS deposit tile carries a two-cell halo, so particles that drifted
+//    up to one cell out of the tile since the sort still deposit into LDS.
+// A particle that moved since the sort is still gathered in its batch, from
+// its own cell, while its stencil lies in the field tile; outside the tile it
+// is queued in LDS for the single-particle path.  After the push, batch
+// particles outside the batch's reference cell queue their deposit.  Queued
+// work runs after the runs, or immediately when a queue is full.
+// Per particle, gathers and pushes add the same terms in the same order as the
+// tiled kernel (explicit fma), so particle states are bit-identical to it.
+#pragma once
+
+#include "k_step_impl.h"
+
+namespace pl {
+
+constexpr int kGQ = 256;                     // particles queued for the single-particle path
+
+template <int PREC> struct RunsQ { static constexpr int DQ = PREC == PL_F32_OFFSET ? 256 : 128; };
+
+// LDS field records, read with 16-byte loads.  Lanes of a wave read
+// records of neighbouring cells, so the record stride decides the bank
+// pattern: float32 charged particles use two planes of 16-byte records
+// (E0 E1 E2 0 | B0 B1 B2 0, the B plane Lf records after the E plane), so 16
+// lanes of one pass cover all 64 banks; float64 charged: one 48-byte record
+// E0 E1 E2 B0 B1 B2; three-component kinds: v0 v1 v2 0.
+template <int PREC, int KIND> struct FieldRec {
+    static constexpr int NC = KIND == PL_LORENTZ ? 6 : 3;
+    static constexpr int FS = PREC == PL_F32_OFFSET ? (NC == 6 ? 8 : 4) : (NC == 6 ? 6 : 4);
+    static constexpr bool PLANES = PREC == PL_F32_OFFSET && NC == 6;
+    // position of component q of cell e in a tile of Lf records
+    __host__ __device__ static constexpr int at(int e, int q, int Lf)
+    {
+        return PLANES ? (q < 3 ? 4 * e + q : 4 * Lf + 4 * e + (q - 3)) : FS * e + q;
+    }
+};
+
+template <int PREC, int KIND>
+__device__ __forceinline__ void load_rec(const typename RealOf<PREC>::T *lds_f, int cell, int Lf,
+                                         typename RealOf<PREC>::T f[FieldRec<PREC, KIND>::NC])
+{
+    if constexpr (PREC == PL_F32_OFFSET) {
+        const float4 *p = reinterpret_cast<const float4 *>(lds_f);
+        if constexpr (KIND == PL_LORENTZ) {
+            float4 a = p[cell], b = p[Lf + cell];
+            f[0] = a.x; f[1] = a.y; f[2] = a.z; f[3] = b.x; f[4] = b.y; f[5] = b.z;
+        } else {
+            float4 a = p[cell];
+            f[0] = a.x; f[1] = a.y; f[2] = a.z;
+        }
+    } else {
+        const double2 *p = reinterpret_cast<const double2 *>(lds_f);
+        if constexpr (KIND == PL_LORENTZ) {
+            double2 a = p[3 * cell], b = p[3 * cell + 1], c = p[3 * cell + 2];
+            f[0] = a.x; f[1] = a.y; f[2] = b.x; f[3] = b.y; f[4] = c.x; f[5] = c.y;
+        } else {
+            double2 a = p[2 * cell], b = p[2 * cell + 1];
+            f[0] = a.x; f[1] = a.y; f[2] = b.x;
+        }
+    }
+}
+
+__device__ __forceinline__ int wrap_any(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// Geometry of one tile: field tile with a one-cell halo, deposit tile with a
+// two-cell halo.
+struct RunGeo {
+    int lo[3], T[3];
+    int fx, fxy, Lf;
+    int dx, dxy, Ld;
+};
+
+// LDS index (field tile) of stencil point (-1,-1,-1) of a particle in cell c,
+// when the whole stencil lies in the field tile (c inside the tile).
+template <int DIM>
+__device__ __forceinline__ bool field_base(const RunGeo &g, const int c[3], int &base)
+{
+    int l0 = c[0] - g.lo[0], l1 = DIM >= 2 ? c[1] - g.lo[1] : 0, l2 = DIM >= 3 ? c[2] - g.lo[2] : 0;
+    bool ok = (unsigned)l0 < (unsigned)g.T[0];
+    if (DIM >= 2) ok = ok && (unsigned)l1 < (unsigned)g.T[1];
+    if (DIM >= 3) ok = ok && (unsigned)l2 < (unsigned)g.T[2];
+    base = l0 + l1 * g.fx + l2 * g.fxy;
+    return ok;
+}
+
+// LDS index (deposit tile) of stencil point (-1,-1,-1), when the stencil lies
+// in the deposit tile (c at most one cell outside the tile, periodically).
+template <int DIM>
+__device__ __forceinline__ bool dep_base(const RunGeo &g, const int n[3], const int c[3], int &base)
+{
+    bool ok = true;
+    int l[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        int v = c[a] - g.lo[a];
+        if (v < -1) v += n[a];
+        else if (v > g.T[a]) v -= n[a];
+        ok = ok && v >= -1 && v <= g.T[a];
+        l[a] = v + 1;
+    }
+    base = l[0] + (DIM >= 2 ? l[1] * g.dx : 0) + (DIM >= 3 ? l[2] * g.dxy : 0);
+    return ok;
+}
+
+template <int DIM>
+__device__ __forceinline__ bool same_cell(const int a[3], const int b[3])
+{
+    bool s = a[0] == b[0];
+    if (DIM >= 2) s = s && a[1] == b[1];
+    if (DIM >= 3) s = s && a[2] == b[2];
+    return s;
+}
+
+// Push of one particle with interpolated fields F (E, B or the gas velocity):
+// updates u, returns the velocity v used for the position update and the
+// deposit values mu (charge / mass, current, force, energy) per channel.
+template <int PREC, int KIND>
+__device__ __forceinline__ void push_particle(const UnitC<PREC> &U, typename RealOf<PREC>::T u[3],
+                                              const typename RealOf<PREC>::T *F, typename RealOf<PREC>::T w,
+                                              typename RealOf<PREC>::T v[3], typename RealOf<PREC>::T mu[kMaxCh])
+{
+    using R = typename RealOf<PREC>::T;
+    if constexpr (KIND == PL_LORENTZ) {
+        R du[3];
+        R uo[3] = {u[0], u[1], u[2]};
+        R u_old2 = fma(u[0], u[0], fma(u[1], u[1], u[2] * u[2]));
+        boris<R>(u, F, F + 3, U.h, U.inv_c2, du);
+        R u_new2 = fma(u[0], u[0], fma(u[1], u[1], u[2] * u[2]));
+        R gn = sqrt(fma(u_new2, U.inv_c2, R(1)));
+        R go = sqrt(fma(u_old2, U.inv_c2, R(1)));
+        R ig = R(1) / gn;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[a] = u[a] * ig;
+        R qw = U.q * w, mw = U.m * w;
+        mu[0] = qw;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            mu[1 + a] = qw * v[a];
+            mu[4 + a] = mw * du[a] * U.inv_dt;
+        }
+        if constexpr (PREC == PL_F64) {
+            mu[7] = mw * U.c2 * (gn - go) * U.inv_dt;
+        } else {
+            R dd = fma(du[0], u[0] + uo[0], fma(du[1], u[1] + uo[1], du[2] * (u[2] + uo[2])));
+            mu[7] = mw * dd / (gn + go) * U.inv_dt;
+        }
+    } else {
+        R du[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            du[a] = (F[a] - u[a]) * U.one_m_decay;
+            u[a] = F[a] + (u[a] - F[a]) * U.decay;
+            v[a] = u[a];
+        }
+        R mw = U.m * w;
+        mu[0] = mw;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            mu[1 + a] = R(0);
+            mu[4 + a] = mw * du[a] * U.inv_dt;
+        }
+        mu[7] = R(0);
+    }
+}
+
+// Offset of channel ch's plane in the LDS deposit tile (compile-time for
+// CHS != 0), -1 when the channel is inactive.
+template <int CHS, class U_>
+__device__ __forceinline__ int ch_off(const U_ &U, int ch, int Ld)
+{
+    if constexpr (CHS != 0) return chs_slot(CHS, ch) >= 0 ? chs_slot(CHS, ch) * Ld : -1;
+    else return U.soff[ch];
+}
+
+template <int PREC> struct RunShared {
+    using R = typename RealOf<PREC>::T;
+    const R *lds_f;
+    double *lds_d;
+    int *gq;
+    uint32_t *dq_c;
+    R *dq_d;      // 3 x DQ
+    R *dq_mu;     // nslot x DQ
+    int *ctl;     // [0] claimed unit, [1] queued particles, [2] queued deposits
+    double *sums; // 8 particle-side sums of the unit
+};
+
+// Particle-side conservation sums (only with SF_SUMS): LDS accumulation per
+// unit, one global add per unit.
+template <int PREC>
+__device__ __forceinline__ void add_sums(const RunShared<PREC> &S, const typename RealOf<PREC>::T mu[kMaxCh])
+{
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        __hip_atomic_fetch_add(S.sums + k, (double)mu[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Interpolate the fields of the LDS field tile to a particle whose stencil
+// starts at record `fb`: the 27 (9 in 2D) records are read kPrefetch points
+// ahead of their use, so several LDS reads are in flight while the previous
+// points are summed.  Terms are added in the order (k, j, i) with explicit
+// fused multiply-adds, the order of the tiled kernel.
+constexpr int kPrefetch = 4;
+
+template <int PREC, int DIM, int KIND>
+__device__ __forceinline__ void gather_rec(const RunGeo &G, const typename RealOf<PREC>::T *lds_f, int fb,
+                                           const typename RealOf<PREC>::T wx[3], const typename RealOf<PREC>::T wy[3],
+                                           const typename RealOf<PREC>::T wz[3],
+                                           typename RealOf<PREC>::T F[FieldRec<PREC, KIND>::NC])
+{
+    using R = typename RealOf<PREC>::T;
+    constexpr int NC = FieldRec<PREC, KIND>::NC;
+    constexpr int SY = Stencil<DIM>::SY, SZ = Stencil<DIM>::SZ;
+    constexpr int NPT = SZ * SY * 3;
+    constexpr int NB = kPrefetch + 1;
+    R buf[NB][NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) F[q] = R(0);
+#pragma unroll
+    for (int pt = 0; pt < kPrefetch && pt < NPT; ++pt)
+        load_rec<PREC, KIND>(lds_f, fb + (pt / 9) * G.fxy + ((pt / 3) % 3) * G.fx + pt % 3, G.Lf, buf[pt % NB]);
+    R wyz = R(0);
+#pragma unroll
+    for (int pt = 0; pt < NPT; ++pt) {
+        const int nx = pt + kPrefetch;
+        if (nx < NPT)
+            load_rec<PREC, KIND>(lds_f, fb + (nx / 9) * G.fxy + ((nx / 3) % 3) * G.fx + nx % 3, G.Lf, buf[nx % NB]);
+        const int k = pt / 9, j = (pt / 3) % 3, i = pt % 3;
+        if (i == 0) wyz = wz[k] * wy[j];
+        const R wt = wyz * wx[i];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) F[q] = fma(wt, buf[pt % NB][q], F[q]);
+    }
+}
+
+// Deposit one particle (cell c, offset d, values mu per channel) into the LDS
+// deposit tile when its stencil fits, else into the grids.
+template <int PREC, int SHAPE, int DIM, int CHS>
+__device__ __forceinline__ void deposit_single(const UnitC<PREC> &U, const RunGeo &G, double *lds_d, const int c[3],
+                                               const typename RealOf<PREC>::T d[3], const double mu[kMaxCh])
+{
+    using R = typename RealOf<PREC>::T;
+    R wx[3], wy[3], wz[3];
+    stencil_weights<PREC, SHAPE, DIM>(d, wx, wy, wz);
+    int base = 0;
+    bool inl = dep_base<DIM>(G, U.n, c, base);
+    deposit<PREC, DIM, CHS>(U, lds_d, inl, base, G.dx, G.dxy, G.Ld, c, wx, wy, wz, mu);
+}
+
+// The whole step of one particle on its own: gather from the LDS field tile
+// when its stencil fits, else from the grids; push; store; deposit.
+template <int PREC, int SHAPE, int DIM, int KIND, int CHS>
+__device__ __forceinline__ void particle_single(const UnitC<PREC> &U, const RunGeo &G, const RunShared<PREC> &S, int p,
+                                             bool do_sums, int &err)
+{
+    using R = typename RealOf<PREC>::T;
+    constexpr int NC = FieldRec<PREC, KIND>::NC;
+    Pos<PREC, DIM> pos;
+    pos.load(U, p, err);
+    R u[3] = {U.u[0][p], U.u[1][p], U.u[2][p]};
+    R w = U.w ? U.w[p] : U.wdef;
+    R d0[3] = {(R)pos.d[0], (R)pos.d[1], (R)pos.d[2]};
+    R wx[3], wy[3], wz[3];
+    stencil_weights<PREC, SHAPE, DIM>(d0, wx, wy, wz);
+    R F[NC];
+    int fb = 0;
+    if (field_base<DIM>(G, pos.c, fb)) {
+        gather_rec<PREC, DIM, KIND>(G, S.lds_f, fb, wx, wy, wz, F);
+    } else {
+        gather<PREC, DIM, NC>(U, nullptr, 0, false, 0, 0, 0, pos.c, wx, wy, wz, F);
+    }
+    R v[3], mu[kMaxCh];
+    push_particle<PREC, KIND>(U, u, F, w, v, mu);
+    if (U.fp[0]) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) U.fp[a][p] = mu[4 + a];
+    }
+    R disp[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) disp[a] = v[a] * U.dtdx[a];
+    pos.advance(disp, U, err);
+    pos.store(U, p);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) U.u[a][p] = u[a];
+    double mud[kMaxCh];
+#pragma unroll
+    for (int ch = 0; ch < kMaxCh; ++ch) mud[ch] = (double)mu[ch];
+    if (do_sums) add_sums(S, mu);
+    R dn[3] = {(R)pos.d[0], (R)pos.d[1], (R)pos.d[2]};
+    deposit_single<PREC, SHAPE, DIM, CHS>(U, G, S.lds_d, pos.c, dn, mud);
+}
+
+// Deposit of a queued record.
+template <int PREC, int SHAPE, int DIM, int CHS>
+__device__ __forceinline__ void record_deposit(const UnitC<PREC> &U, const RunGeo &G, const RunShared<PREC> &S, int i)
+{
+    using R = typename RealOf<PREC>::T;
+    constexpr int DQ = RunsQ<PREC>::DQ;
+    int c[3];
+    unpack_cell(S.dq_c[i], c[0], c[1], c[2]);
+    R d[3] = {S.dq_d[i], S.dq_d[DQ + i], S.dq_d[2 * DQ + i]};
+    double mu[kMaxCh];
+#pragma unroll
+    for (int ch = 0; ch < kMaxCh; ++ch) {
+        int so = ch_off<CHS>(U, ch, G.Ld);
+        mu[ch] = so >= 0 ? (double)S.dq_mu[(so / G.Ld) * DQ + i] : 0.0;
+    }
+    deposit_single<PREC, SHAPE, DIM, CHS>(U, G, S.lds_d, c, d, mu);
+}
+
+// Deposit of the batch particles in the reference cell (dco[j]): their values
+// are summed per stencil point and channel before each LDS atomic.
+template <int PREC, int SHAPE, int DIM, int CHS, int KR>
+__device__ __forceinline__ void batch_deposit(const UnitC<PREC> &U, const RunGeo &G, const RunShared<PREC> &S, int db,
+                                              const Pos<PREC, DIM> pos[KR], typename RealOf<PREC>::T mu[KR][kMaxCh],
+                                              const bool dco[KR])
+{
+    using R = typename RealOf<PREC>::T;
+    constexpr int SY = Stencil<DIM>::SY, SZ = Stencil<DIM>::SZ;
+    R wx[KR][3], wy[KR][3], wz[KR][3];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        R dn[3] = {(R)pos[j].d[0], (R)pos[j].d[1], (R)pos[j].d[2]};
+        stencil_weights<PREC, SHAPE, DIM>(dn, wx[j], wy[j], wz[j]);
+#pragma unroll
+        for (int ch = 0; ch < kMaxCh; ++ch) mu[j][ch] = dco[j] ? mu[j][ch] : R(0);
+    }
+#pragma unroll
+    for (int k = 0; k < SZ; ++k)
+#pragma unroll
+        for (int jj = 0; jj < SY; ++jj) {
+            R wyz[KR];
+#pragma unroll
+            for (int j = 0; j < KR; ++j) wyz[j] = wz[j][k] * wy[j][jj];
+            const int row = db + k * G.dxy + jj * G.dx;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                R wt[KR];
+#pragma unroll
+                for (int j = 0; j < KR; ++j) wt[j] = wyz[j] * wx[j][i];
+#pragma unroll
+                for (int ch = 0; ch < kMaxCh; ++ch) {
+                    const int so = ch_off<CHS>(U, ch, G.Ld);
+                    if (so < 0) continue;
+                    R s = wt[0] * mu[0][ch];
+#pragma unroll
+                    for (int j = 1; j < KR; ++j) s = fma(wt[j], mu[j][ch], s);
+                    __hip_atomic_fetch_add(S.lds_d + so + row + i, (double)s, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+        }
+}
+
+// Gather, push and deposit of the batch particles whose stencil lies in the
+// LDS field tile (co[j]); fb[j] is the field record of stencil point
+// (-1,-1,-1) of particle j.
+template <int PREC, int SHAPE, int DIM, int KIND, int CHS, int KR>
+__device__ __forceinline__ void batch_body(const UnitC<PREC> &U, const RunGeo &G, const RunShared<PREC> &S, int start,
+                                           const int fb[KR], Pos<PREC, DIM> pos[KR], typename RealOf<PREC>::T u[KR][3],
+                                           const typename RealOf<PREC>::T w[KR], const bool co[KR], bool do_sums, int &err)
+{
+    using R = typename RealOf<PREC>::T;
+    constexpr int NC = FieldRec<PREC, KIND>::NC;
+    constexpr int SY = Stencil<DIM>::SY, SZ = Stencil<DIM>::SZ;
+    constexpr int DQ = RunsQ<PREC>::DQ;
+
+    // gather and push one particle at a time (each stencil point is one
+    // interleaved LDS record read); keep what the batched deposit needs
+    R mu[KR][kMaxCh];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        const int p = start + j;
+        R wx[3], wy[3], wz[3];
+        R d0[3] = {(R)pos[j].d[0], (R)pos[j].d[1], (R)pos[j].d[2]};
+        stencil_weights<PREC, SHAPE, DIM>(d0, wx, wy, wz);
+        R F[NC];
+        gather_rec<PREC, DIM, KIND>(G, S.lds_f, fb[j], wx, wy, wz, F);
+        R v[3];
+        push_particle<PREC, KIND>(U, u[j], F, w[j], v, mu[j]);
+        R disp[3] = {R(0), R(0), R(0)};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) disp[a] = v[a] * U.dtdx[a];
+        int e2 = 0;
+        pos[j].advance(disp, U, e2);
+        if (co[j]) {
+            err |= e2;
+            pos[j].store(U, p);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) U.u[a][p] = u[j][a];
+            if (U.fp[0]) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) U.fp[a][p] = mu[j][4 + a];
+            }
+            if (do_sums) add_sums(S, mu[j]);
+        }
+    }
+
+    // deposit: the batch particles in the reference cell are summed before
+    // each LDS atomic; the others are queued.  The reference is the new cell
+    // of the first batch particle, or of the second when the first shares its
+    // cell with no other batch particle.
+    int f0 = -1, f1 = -1;
+#pragma unroll
+    for (int j = KR - 1; j >= 0; --j) {
+        if (co[j]) {
+            f1 = f0;
+            f0 = j;
+        }
+    }
+    int rc[3] = {0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < KR; ++j)
+        if (j == f0)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) rc[a] = pos[j].c[a];
+    bool alone = true;
+#pragma unroll
+    for (int j = 0; j < KR; ++j) alone = alone && (j == f0 || !(co[j] && same_cell<DIM>(pos[j].c, rc)));
+    if (alone && f1 >= 0) {
+#pragma unroll
+        for (int j = 0; j < KR; ++j)
+            if (j == f1)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) rc[a] = pos[j].c[a];
+    }
+    int db = 0;
+    const bool dep_in = dep_base<DIM>(G, U.n, rc, db);
+    bool dco[KR];
+    bool any_dco = false;
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        dco[j] = co[j] && dep_in && same_cell<DIM>(pos[j].c, rc);
+        any_dco = any_dco || dco[j];
+    }
+    unsigned ovf_d = 0;
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        if (co[j] && !dco[j]) {
+            int q = atomicAdd(&S.ctl[2], 1);
+            if (q < DQ) {
+                S.dq_c[q] = pack_cell(pos[j].c[0], DIM > 1 ? pos[j].c[1] : 0, DIM > 2 ? pos[j].c[2] : 0);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) S.dq_d[a * DQ + q] = (R)pos[j].d[a];
+#pragma unroll
+                for (int ch = 0; ch < kMaxCh; ++ch) {
+                    int so = ch_off<CHS>(U, ch, G.Ld);
+                    if (so >= 0) S.dq_mu[(so / G.Ld) * DQ + q] = mu[j][ch];
+                }
+            } else {
+                ovf_d |= 1u << j;
+            }
+        }
+    }
+    // deposits that found the queue full
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        if (ovf_d & (1u << j)) {
+            double mud[kMaxCh];
+#pragma unroll
+            for (int ch = 0; ch < kMaxCh; ++ch) mud[ch] = (double)mu[j][ch];
+            R dn[3] = {(R)pos[j].d[0], (R)pos[j].d[1], (R)pos[j].d[2]};
+            deposit_single<PREC, SHAPE, DIM, CHS>(U, G, S.lds_d, pos[j].c, dn, mud);
+        }
+    }
+    if (any_dco) batch_deposit<PREC, SHAPE, DIM, CHS, KR>(U, G, S, db, pos, mu, dco);
+}
+
+// One run: batches of KR particles of one cell.
+template <int PREC, int SHAPE, int DIM, int KIND, int CHS, int KR>
+__device__ __forceinline__ void run_batch(const UnitC<PREC> &U, const RunGeo &G, const RunShared<PREC> &S, int start,
+                                          int len, bool do_sums, int &err)
+{
+    using R = typename RealOf<PREC>::T;
+    Pos<PREC, DIM> pos[KR];
+    R u[KR][3], w[KR];
+    pos[0].load(U, start, err);
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        const int p = start + j;
+        if (j > 0) {
+            if (j < len) pos[j].load(U, p, err);
+            else pos[j] = pos[0];
+        }
+        const bool in = j < len;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[j][a] = in ? U.u[a][p] : R(0);
+        w[j] = in ? (U.w ? U.w[p] : U.wdef) : R(0);
+    }
+    // every particle whose stencil lies in the LDS field tile is gathered in
+    // the batch from its own cell (lanes read distinct records anyway)
+    int fb[KR];
+    bool co[KR];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        co[j] = field_base<DIM>(G, pos[j].c, fb[j]) && j < len;
+        if (!co[j]) fb[j] = 0;       // computed but unused: keep its reads inside the field tile
+    }
+    // particles outside the tile: queue for the single-particle path (when
+    // the queue is full they run on their own after the batch)
+    unsigned ovf_g = 0;
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        if (j < len && !co[j]) {
+            int q = atomicAdd(&S.ctl[1], 1);
+            if (q < kGQ) S.gq[q] = start + j;
+            else ovf_g |= 1u << j;
+        }
+    }
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < KR; ++j) any = any || co[j];
+    if (any) batch_body<PREC, SHAPE, DIM, KIND, CHS, KR>(U, G, S, start, fb, pos, u, w, co, do_sums, err);
+    while (ovf_g) {
+        const int j = __builtin_ctz(ovf_g);
+        ovf_g &= ovf_g - 1u;
+        particle_single<PREC, SHAPE, DIM, KIND, CHS>(U, G, S, start + j, do_sums, err);
+    }
+}
+
+// LDS bytes of one work unit: field records, float64 deposit tile, queues,
+// a 16-byte control tail.
+__host__ __device__ inline size_t runs_section(size_t b) { return (b + 15) & ~(size_t)15; }
+
+template <int PREC, int KIND>
+__host__ __device__ inline size_t runs_lds_bytes(int Lf, int Ld, int nslot, size_t offs[6])
+{
+    using R = typename RealOf<PREC>::T;
+    constexpr int DQ = RunsQ<PREC>::DQ;
+    size_t o = 0;
+    offs[0] = o; o += runs_section((size_t)Lf * FieldRec<PREC, KIND>::FS * sizeof(R));
+    offs[1] = o; o += runs_section((size_t)Ld * nslot * sizeof(double));
+    offs[2] = o; o += runs_section((size_t)kGQ * sizeof(int));
+    offs[3] = o; o += runs_section((size_t)DQ * sizeof(uint32_t));
+    offs[4] = o; o += runs_section((size_t)DQ * (3 + nslot) * sizeof(R));
+    offs[5] = o; o += 8 * sizeof(double);
+    return o + 16;
+}
+
+// One block per CU (the LDS tiles take most of the 160 KB), so RB / 256
+// waves per SIMD: the compiler may spend registers on reads in flight.
+template <int PREC, int SHAPE, int DIM, int KIND, int RB, int TS, int CHS>
+__global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(RB / 256, RB / 256))) void k_runs(const ItemDesc *__restrict__ items, int nitems, int total_units,
+                                             unsigned *counter, int *errflags, unsigned flags, int lds_bytes)
+{
+    using R = typename RealOf<PREC>::T;
+    using FR = FieldRec<PREC, KIND>;
+    constexpr int NC = FR::NC, FS = FR::FS;
+    constexpr int KR = PREC == PL_F32_OFFSET ? 4 : 2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int *ctl = reinterpret_cast<int *>(smem_raw + lds_bytes - 16);
+    const bool do_sums = flags & SF_SUMS;
+    int err = 0;
+
+    for (;;) {
+        int g = claim_unit(counter, total_units, ctl);
+        if (g < 0) break;
+        const int iti = find_item(items, nitems, g);
+        const ItemDesc &I = items[iti];
+        const int t = g - I.unit_begin;
+        RunGeo G;
+        G.T[0] = TS ? ts_dim(TS, 0) : I.tile[0];
+        G.T[1] = TS ? ts_dim(TS, 1) : I.tile[1];
+        G.T[2] = TS ? ts_dim(TS, 2) : I.tile[2];
+        {
+            int tx = t % I.ntile[0];
+            int ty = (t / I.ntile[0]) % I.ntile[1];
+            int tz = t / (I.ntile[0] * I.ntile[1]);
+            G.lo[0] = tx * G.T[0];
+            G.lo[1] = ty * G.T[1];
+            G.lo[2] = tz * G.T[2];
+        }
+        G.fx = G.T[0] + 2;
+        G.fxy = G.fx * (G.T[1] + 2);
+        G.Lf = G.fxy * (DIM >= 3 ? G.T[2] + 2 : 1);
+        G.dx = G.T[0] + 4;
+        G.dxy = G.dx * (G.T[1] + 4);
+        G.Ld = G.dxy * (DIM >= 3 ? G.T[2] + 4 : 1);
+        const int pbeg = min(max(I.tile_start[t], 0), I.np);
+        const int pend = min(max(I.tile_start[t + 1], pbeg), I.np);
+        const int nruns = min(max(I.runs[I.np + t], 0), pend - pbeg);
+        if (nruns == 0) continue;          // uniform: the whole block skips an empty tile
+
+        UnitC<PREC> U;
+        load_unit<PREC>(I, U, G.Ld);
+        const int nslot = I.nslot;
+        size_t offs[6];
+        runs_lds_bytes<PREC, KIND>(G.Lf, G.Ld, nslot, offs);
+        RunShared<PREC> S;
+        R *lds_f = reinterpret_cast<R *>(smem_raw + offs[0]);
+        S.lds_f = lds_f;
+        S.lds_d = reinterpret_cast<double *>(smem_raw + offs[1]);
+        S.gq = reinterpret_cast<int *>(smem_raw + offs[2]);
+        S.dq_c = reinterpret_cast<uint32_t *>(smem_raw + offs[3]);
+        S.dq_d = reinterpret_cast<R *>(smem_raw + offs[4]);
+        S.dq_mu = S.dq_d + 3 * RunsQ<PREC>::DQ;
+        S.ctl = ctl;
+        S.sums = reinterpret_cast<double *>(smem_raw + offs[5]);
+
+        // stage the field records (one-cell halo) and clear the deposit tile
+        {
+            const int Ly = G.T[1] + 2;
+            for (int e = threadIdx.x; e < G.Lf; e += blockDim.x) {
+                int lx = e % G.fx;
+                int ly = (e / G.fx) % Ly;
+                int lz = e / G.fxy;
+                int gx = wrap_any(G.lo[0] + lx - 1, U.n[0]);
+                int gy = DIM >= 2 ? wrap_any(G.lo[1] + ly - 1, U.n[1]) : 0;
+                int gz = DIM >= 3 ? wrap_any(G.lo[2] + lz - 1, U.n[2]) : 0;
+                long gc = gx + (long)U.n[0] * (gy + (long)U.n[1] * gz);
+#pragma unroll
+                for (int q = 0; q < NC; ++q) lds_f[FR::at(e, q, G.Lf)] = (R)U.gf[q][gc];
+                if constexpr (FR::PLANES) {
+                    lds_f[FR::at(e, 0, G.Lf) + 3] = R(0);
+                    lds_f[FR::at(e, 3, G.Lf) + 3] = R(0);
+                } else {
+#pragma unroll
+                    for (int s = NC; s < FS; ++s) lds_f[FS * e + s] = R(0);
+                }
+            }
+            for (int e = threadIdx.x; e < G.Ld * nslot; e += blockDim.x) S.lds_d[e] = 0.0;
+            if (threadIdx.x == 0) {
+                ctl[1] = 0;
+                ctl[2] = 0;
+            }
+            if (threadIdx.x < 8) S.sums[threadIdx.x] = 0.0;
+            __syncthreads();
+        }
+
+        const int32_t *runs = I.runs + pbeg;
+        for (int r = threadIdx.x; r < nruns; r += blockDim.x) {
+            const int e = runs[r];
+            int start = e >> 2;
+            int len = (e & 3) + 1;
+            start = min(max(start, pbeg), pend - 1);
+            len = min(len, pend - start);
+            for (int b = 0; b < len; b += KR)
+                run_batch<PREC, SHAPE, DIM, KIND, CHS, KR>(U, G, S, start + b, min(KR, len - b), do_sums, err);
+        }
+        __syncthreads();
+        const int ng = min(ctl[1], kGQ);
+        for (int i = threadIdx.x; i < ng; i += blockDim.x)
+            particle_single<PREC, SHAPE, DIM, KIND, CHS>(U, G, S, S.gq[i], do_sums, err);
+        const int nd = min(ctl[2], RunsQ<PREC>::DQ);
+        for (int i = threadIdx.x; i < nd; i += blockDim.x) record_deposit<PREC, SHAPE, DIM, CHS>(U, G, S, i);
+
+        // flush the deposit tile: one float64 global atomic per touched cell and channel
+        __syncthreads();
+        if (do_sums && threadIdx.x < 8 && S.sums[threadIdx.x] != 0.0) global_add(I.psum + threadIdx.x, S.sums[threadIdx.x]);
+        {
+            const int Ly = G.T[1] + 4;
+            for (int e = threadIdx.x; e < G.Ld; e += blockDim.x) {
+                int lx = e % G.dx;
+                int ly = (e / G.dx) % Ly;
+                int lz = e / G.dxy;
+                int gx = wrap_any(G.lo[0] + lx - 2, U.n[0]);
+                int gy = DIM >= 2 ? wrap_any(G.lo[1] + ly - 2, U.n[1]) : 0;
+                int gz = DIM >= 3 ? wrap_any(G.lo[2] + lz - 2, U.n[2]) : 0;
+                long gc = gx + (long)U.n[0] * (gy + (long)U.n[1] * gz);
+#pragma unroll
+                for (int ch = 0; ch < kMaxCh; ++ch) {
+                    const int so = ch_off<CHS>(U, ch, G.Ld);
+                    if (so < 0) continue;
+                    double val = S.lds_d[so + e];
+                    if (val != 0.0) global_add(U.M[ch] + gc, val * U.inv_dv);
+                }
+            }
+        }
+    }
+
+    unsigned long long any = __ballot(err != 0);
+    if (any) {
+        int e = err;
+        for (int off = 32; off > 0; off >>= 1) e |= __shfl_xor(e, off, 64);
+        if ((threadIdx.x & 63) == 0) atomicOr(errflags, e);
+    }
+    release_counter(counter);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+template <int PREC>
+static StepKernel pick_runs(int shape, int dim, int kind, int rb, int ts, int chs)
+{
+#define PL_R(S, D, K, RB_, TS_, CHS_) \
+    if (shape == S && dim == D && kind == K && rb == RB_ && ts == TS_ && chs == CHS_) \
+        return k_runs<PREC, S, D, K, RB_, TS_, CHS_>;
+#define PL_RG(S, D) PL_R(S, D, PL_LORENTZ, 512, 0, 0) PL_R(S, D, PL_DUST, 512, 0, 0)
+#define PL_RF(TS_) PL_R(PL_TSC, 3, PL_LORENTZ, 1024, TS_, 1) PL_R(PL_TSC, 3, PL_LORENTZ, 512, TS_, 1) \
+    PL_R(PL_TSC, 3, PL_DUST, 1024, TS_, 2) PL_R(PL_TSC, 3, PL_DUST, 512, TS_, 2)
+    PL_RG(PL_TSC, 3) PL_RG(PL_TSC, 2) PL_RG(PL_CIC, 3) PL_RG(PL_CIC, 2)
+    PL_RF(1) PL_RF(2)
+#undef PL_RF
+#undef PL_RG
+#undef PL_R
+    return nullptr;
+}
+
+template <int PREC>
+hipError_t launch_runs_impl(Ctx *c, const ItemDesc *table, const ItemDesc *host, int nitems, int total_units,
+                            unsigned sf, unsigned *counter)
+{
+    if (total_units <= 0) return hipSuccess;
+    const int kind = host[0].kind;
+    if (kind == PL_TRACER) return hipErrorInvalidConfiguration;
+    // compile-time tile shape (8^3 or 8x8x4) and channel set when every item
+    // of the group allows them; the generic kernel otherwise
+    int ts = 0, chs = 0;
+    if (c->d.shape == PL_TSC && c->d.ndim == 3) {
+        int want = kind == PL_LORENTZ ? 1 : 2;
+        bool chall = true;
+        for (int i = 0; i < nitems && chall; ++i)
+            for (int ch = 0; ch < kMaxCh; ++ch) chall = chall && host[i].slot[ch] == chs_slot(want, ch);
+        for (int cand = 1; cand <= 2 && ts == 0 && chall; ++cand) {
+            bool all = true;
+            for (int i = 0; i < nitems; ++i)
+                for (int a = 0; a < 3; ++a) all = all && host[i].tile[a] == ts_dim(cand, a);
+            if (all) {
+                ts = cand;
+                chs = want;
+            }
+        }
+    }
+    const int rb = (ts != 0 && c->runs_block == 1024) ? 1024 : 512;
+    StepKernel k = pick_runs<PREC>(c->d.shape, c->d.ndim, kind, rb, ts, chs);
+    if (!k) return hipErrorInvalidConfiguration;
+    size_t lds = 0;
+    for (int i = 0; i < nitems; ++i) {
+        const ItemDesc &it = host[i];
+        const int d3 = c->d.ndim >= 3;
+        int Lf = (it.tile[0] + 2) * (it.tile[1] + 2) * (d3 ? it.tile[2] + 2 : 1);
+        int Ld = (it.tile[0] + 4) * (it.tile[1] + 4) * (d3 ? it.tile[2] + 4 : 1);
+        size_t offs[6];
+        size_t b = kind == PL_LORENTZ ? runs_lds_bytes<PREC, PL_LORENTZ>(Lf, Ld, it.nslot, offs)
+                                      : runs_lds_bytes<PREC, PL_DUST>(Lf, Ld, it.nslot, offs);
+        lds = std::max(lds, b);
+    }
+    if (lds > (size_t)c->lds_max) return hipErrorInvalidConfiguration;
+    int grid = std::min(total_units, resident_blocks(c, k, rb, lds));
+    hipLaunchKernelGGL(k, dim3(grid), dim3(rb), lds, c->stream, table, nitems, total_units, counter, c->errflags, sf,
+                       (int)lds);
+    c->stats[0]++;
+    c->stats[4]++;
+    return hipGetLastError();
+}
+
+}  // namespace pl

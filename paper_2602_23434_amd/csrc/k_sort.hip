@@ -237,6 +237,69 @@ __global__ void k_rank_keys(uint32_t *keys, int np, const int32_t *cs, int cell_
     }
 }
 
+// Run table of one tile per block (keys sorted by tile * cells_per_tile + cell
+// in tile): the particles of every cell are cut into runs of up to kRunLen
+// consecutive positions, and the runs are listed by (index of the run inside
+// its cell, cell), so consecutive runs belong to distinct cells.  Entry:
+// (first position << 2) | (length - 1), stored from runs[tile_start[t]];
+// the tile's run count goes to runs[np + t].
+constexpr int kRunsBuildThreads = 256;
+__global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t *keys, int np, int per_tile,
+                                                                  int ntiles, const int32_t *ts, int32_t *runs)
+{
+    __shared__ int cnt[kRunsMaxTileCells];
+    __shared__ int first[kRunsMaxTileCells];
+    __shared__ uint32_t sh[kRunsBuildThreads / 64 + 1];
+    __shared__ int s_max;
+    const int cpt = (per_tile + kRunsBuildThreads - 1) / kRunsBuildThreads;   // cells per thread
+    const int c0 = threadIdx.x * cpt, c1 = min(per_tile, c0 + cpt);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int beg = ts[t], end = ts[t + 1];
+        for (int c = threadIdx.x; c < per_tile; c += blockDim.x) cnt[c] = 0;
+        if (threadIdx.x == 0) s_max = 0;
+        __syncthreads();
+        const uint32_t kb = (uint32_t)t * (uint32_t)per_tile;
+        for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
+            uint32_t loc = keys[p] - kb;
+            if (loc < (uint32_t)per_tile) atomicAdd(&cnt[loc], 1);
+        }
+        __syncthreads();
+        // first sorted position of every cell, and the largest run count
+        uint32_t mine = 0;
+        int mx = 0;
+        for (int c = c0; c < c1; ++c) {
+            mine += (uint32_t)cnt[c];
+            mx = max(mx, (cnt[c] + kRunLen - 1) / kRunLen);
+        }
+        uint32_t total;
+        uint32_t run = block_exclusive_scan(mine, sh, total);
+        for (int c = c0; c < c1; ++c) {
+            first[c] = beg + (int)run;
+            run += (uint32_t)cnt[c];
+        }
+        atomicMax(&s_max, mx);
+        __syncthreads();
+        const int nb = s_max;
+        int base = 0;
+        for (int b = 0; b < nb; ++b) {
+            uint32_t here = 0;
+            for (int c = c0; c < c1; ++c) here += cnt[c] > b * kRunLen;
+            uint32_t pos = block_exclusive_scan(here, sh, total);
+            for (int c = c0; c < c1; ++c) {
+                int left = cnt[c] - b * kRunLen;
+                if (left > 0) {
+                    int len = min(kRunLen, left);
+                    runs[beg + base + (int)pos] = ((first[c] + b * kRunLen) << 2) | (len - 1);
+                    ++pos;
+                }
+            }
+            base += (int)total;
+        }
+        if (threadIdx.x == 0) runs[np + t] = base;
+        __syncthreads();
+    }
+}
+
 __global__ void k_fill_i32(int32_t *p, int n, int v)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
@@ -282,6 +345,11 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
         hipLaunchKernelGGL(k_fill_i32, dim3(std::max(1, (a.ntiles + 256) / 256)), dim3(256), 0, s, a.tile_start,
                            a.ntiles + 1, 0);
         c->stats[0]++;
+        if (a.runs) {
+            hipLaunchKernelGGL(k_fill_i32, dim3(std::max(1, (a.ntiles + 256) / 256)), dim3(256), 0, s, a.runs,
+                               a.ntiles, 0);
+            c->stats[0]++;
+        }
         return hipGetLastError();
     }
     const int per_tile_cells = a.tile[0] * a.tile[1] * a.tile[2];
@@ -318,6 +386,12 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
     hipLaunchKernelGGL(k_tile_start, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, shift, div, a.ntiles,
                        a.tile_start);
     c->stats[0]++;
+    if (a.runs) {
+        // keys are tile * cells_per_tile + cell in tile (PL_KEY_TILE_CELL)
+        hipLaunchKernelGGL(k_runs_build, dim3(std::min(a.ntiles, 8 * c->num_cu)), dim3(kRunsBuildThreads), 0, s,
+                           c->keys[src], a.np, per_tile_cells, a.ntiles, a.tile_start, a.runs);
+        c->stats[0]++;
+    }
     return hipGetLastError();
 }
 

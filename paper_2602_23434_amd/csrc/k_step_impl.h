@@ -591,7 +591,7 @@ hipError_t launch_group_impl(Ctx *c, const ItemDesc *table, const ItemDesc *host
                              unsigned sf, bool push, bool deposit, unsigned *counter)
 {
     if (total_units <= 0) return hipSuccess;
-    const bool tiled = c->d.algo == PL_ALGO_TILED;
+    const bool tiled = c->d.algo != PL_ALGO_PLAIN;
     const int kind = host[0].kind;
     // compile-time tile shape and channel set when every item of the group allows them
     int ts = 0, chs = 0;

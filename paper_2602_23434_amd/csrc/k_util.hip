@@ -13,6 +13,10 @@ hipError_t launch_group_f32(Ctx *c, const ItemDesc *table, const ItemDesc *host,
                             unsigned sf, bool push, bool deposit, unsigned *counter);
 hipError_t launch_group_f64(Ctx *c, const ItemDesc *table, const ItemDesc *host, int nitems, int total_units,
                             unsigned sf, bool push, bool deposit, unsigned *counter);
+hipError_t launch_runs_f32(Ctx *c, const ItemDesc *table, const ItemDesc *host, int nitems, int total_units,
+                           unsigned sf, unsigned *counter);
+hipError_t launch_runs_f64(Ctx *c, const ItemDesc *table, const ItemDesc *host, int nitems, int total_units,
+                           unsigned sf, unsigned *counter);
 
 // The host table is ordered by species kind, then by particle count; every
 // run of one kind is one launch with its own work counter.
@@ -27,11 +31,23 @@ hipError_t launch_step(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc
         int i1 = i0;
         int units = 0;
         while (i1 < nitems && host[i1].kind == host[i0].kind) units += host[i1++].nunits;
-        hipError_t e = c->d.prec == PL_F64
-                           ? launch_group_f64(c, table + i0, host.data() + i0, i1 - i0, units, sf, push, deposit,
-                                              c->counters + 2 * group)
-                           : launch_group_f32(c, table + i0, host.data() + i0, i1 - i0, units, sf, push, deposit,
-                                              c->counters + 2 * group);
+        // the run-based kernel takes fused steps of charged and dust species;
+        // everything else (and a tile too large for its LDS) takes the tiled one
+        hipError_t e = hipErrorInvalidConfiguration;
+        if (c->d.algo == PL_ALGO_RUNS && push && deposit && host[i0].kind != PL_TRACER)
+            e = c->d.prec == PL_F64 ? launch_runs_f64(c, table + i0, host.data() + i0, i1 - i0, units, sf,
+                                                      c->counters + 2 * group)
+                                    : launch_runs_f32(c, table + i0, host.data() + i0, i1 - i0, units, sf,
+                                                      c->counters + 2 * group);
+        if (e == hipErrorInvalidConfiguration && c->d.algo == PL_ALGO_RUNS && push && deposit &&
+            host[i0].kind != PL_TRACER)
+            c->stats[5]++;
+        if (e == hipErrorInvalidConfiguration)
+            e = c->d.prec == PL_F64
+                    ? launch_group_f64(c, table + i0, host.data() + i0, i1 - i0, units, sf, push, deposit,
+                                       c->counters + 2 * group)
+                    : launch_group_f32(c, table + i0, host.data() + i0, i1 - i0, units, sf, push, deposit,
+                                       c->counters + 2 * group);
         if (e != hipSuccess) return e;
         i0 = i1;
         ++group;

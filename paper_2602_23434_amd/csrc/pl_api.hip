@@ -32,14 +32,20 @@ pl_status validate_desc(const pl_init_desc *d)
     if (d->ndim != 2 && d->ndim != 3) return PL_EINVAL;
     if (d->prec != PL_F64 && d->prec != PL_F32_OFFSET) return PL_EINVAL;
     if (d->shape != PL_CIC && d->shape != PL_TSC) return PL_EINVAL;
-    if (d->algo != PL_ALGO_PLAIN && d->algo != PL_ALGO_TILED) return PL_EINVAL;
+    if (d->algo != PL_ALGO_PLAIN && d->algo != PL_ALGO_TILED && d->algo != PL_ALGO_RUNS) return PL_EINVAL;
+    if (d->algo == PL_ALGO_RUNS && (d->key_mode != PL_KEY_TILE_CELL || d->max_np >= (int64_t)1 << 29))
+        return PL_EINVAL;
     if (d->key_mode != PL_KEY_TILE && d->key_mode != PL_KEY_TILE_CELL && d->key_mode != PL_KEY_TILE_RANK)
         return PL_EINVAL;
     if (!finite_pos(d->c)) return PL_EINVAL;
     if (d->nboxes < 1 || !d->boxes || d->nspecies < 1 || !d->species) return PL_EINVAL;
     if (d->max_items < 1 || d->max_items > 4096) return PL_EINVAL;
     if (d->max_np < 0 || d->max_np >= (int64_t)1 << 31) return PL_EINVAL;
-    if (d->block != 0 && (d->block < 64 || d->block > 512 || d->block % 64)) return PL_EINVAL;
+    if (d->algo == PL_ALGO_RUNS) {
+        if (d->block != 0 && d->block != 512 && d->block != 1024) return PL_EINVAL;
+    } else if (d->block != 0 && (d->block < 64 || d->block > 512 || d->block % 64)) {
+        return PL_EINVAL;
+    }
     for (int b = 0; b < d->nboxes; ++b) {
         const pl_box_desc &x = d->boxes[b];
         for (int a = 0; a < 3; ++a) {
@@ -68,7 +74,7 @@ int divisor_at_most(int n, int want)
     return 1;
 }
 
-void read_tune_cache(const char *path, int &block, int tile[3], int &runs)
+void read_tune_cache(const char *path, int &block, int tile[3], int &runs, int &runs_block)
 {
     if (!path) return;
     FILE *f = fopen(path, "r");
@@ -81,6 +87,9 @@ void read_tune_cache(const char *path, int &block, int tile[3], int &runs)
         } else if (!strcmp(key, "runs")) {
             int v;
             if (fscanf(f, "%d", &v) == 1) runs = v != 0;
+        } else if (!strcmp(key, "runs_block")) {
+            int v;
+            if (fscanf(f, "%d", &v) == 1 && (v == 512 || v == 1024)) runs_block = v;
         } else if (!strcmp(key, "tile")) {
             int a, b, c;
             if (fscanf(f, "%d %d %d", &a, &b, &c) == 3 && a > 0 && b > 0 && c > 0) {
@@ -151,7 +160,8 @@ pl_status make_desc(const Ctx *c, const pl_item &it, double dt, Mode mode, bool 
     if (nfp != 0 && nfp != 3) return PL_EINVAL;
     for (int a = 0; a < 3; ++a)
         if (!chk(p.fp[a], es, false)) return PL_EINVAL;
-    if (d.algo == PL_ALGO_TILED && !chk(p.tile_start, 4, true)) return PL_EINVAL;
+    if (d.algo != PL_ALGO_PLAIN && !chk(p.tile_start, 4, true)) return PL_EINVAL;
+    if (d.algo == PL_ALGO_RUNS && !chk(p.runs, 4, true)) return PL_EINVAL;
 
     // fields the kind reads (only when pushing)
     if (mode == MODE_STEP) {
@@ -213,6 +223,7 @@ pl_status make_desc(const Ctx *c, const pl_item &it, double dt, Mode mode, bool 
     }
     D.w = p.w[cur];
     D.tile_start = p.tile_start;
+    D.runs = p.runs;
     D.nslot = 0;
     for (int ch = 0; ch < kMaxCh; ++ch) {
         D.M[ch] = M[ch];
@@ -246,7 +257,7 @@ pl_status build_table(Ctx *c, const pl_item *items, int nitems, double dt, Mode 
     });
     host.clear();
     total_units = 0;
-    const bool tiled = c->d.algo == PL_ALGO_TILED;
+    const bool tiled = c->d.algo != PL_ALGO_PLAIN;
     const int chunk = c->block * 4;
     int group_units = 0;
     for (int k = 0; k < nitems; ++k) {
@@ -388,17 +399,24 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d)
     c->stream = (hipStream_t)d->stream;
     c->max_np = d->max_np;
 
-    int tuned_block = 256, tuned_tile[3] = {8, 8, 8}, tuned_runs = 0;
+    int tuned_block = 256, tuned_tile[3] = {8, 8, 8}, tuned_runs = 0, tuned_runs_block = 512;
     if (d->prec == PL_F64 && d->algo == PL_ALGO_TILED) { tuned_tile[1] = 4; tuned_tile[2] = 4; }
-    read_tune_cache(d->tune_cache, tuned_block, tuned_tile, tuned_runs);
-    c->block = d->block ? d->block : tuned_block;
+    if (d->prec == PL_F64 && d->algo == PL_ALGO_RUNS) tuned_tile[2] = 4;
+    read_tune_cache(d->tune_cache, tuned_block, tuned_tile, tuned_runs, tuned_runs_block);
+    const bool runs_algo = d->algo == PL_ALGO_RUNS;
+    c->block = (d->block && !runs_algo) ? d->block : tuned_block;
     c->runs = tuned_runs != 0;
+    c->runs_block = (d->block && runs_algo) ? d->block : tuned_runs_block;
     for (auto &b : c->boxes) {
         if (b.tile[0] == 0) {
             for (int a = 0; a < 3; ++a) b.tile[a] = divisor_at_most(b.n[a], tuned_tile[a]);
             if (d->ndim == 2) b.tile[2] = 1;
         }
         c->max_ntiles = std::max(c->max_ntiles, (b.n[0] / b.tile[0]) * (b.n[1] / b.tile[1]) * (b.n[2] / b.tile[2]));
+        if (d->algo == PL_ALGO_RUNS && b.tile[0] * b.tile[1] * b.tile[2] > kRunsMaxTileCells) {
+            delete c;
+            return PL_EUNSUPPORTED;
+        }
     }
     int64_t max_cells = 0;
     for (const auto &b : c->boxes) {
@@ -504,6 +522,7 @@ pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems)
         a.ntiles = D.ntiles;
         a.cell = p.cell[cur];
         a.tile_start = p.tile_start;
+        a.runs = c->d.algo == PL_ALGO_RUNS ? p.runs : nullptr;
         auto add = [&](const void *s, void *dd, int esz) -> bool {
             if (!s) return true;
             if (!dd || !aligned(dd, (size_t)esz) || a.narrays >= SortArgs::kMaxArrays) return false;
@@ -615,11 +634,11 @@ pl_status pl_part_set_stream(pl_ctx *ctx, void *stream)
     return PL_OK;
 }
 
-pl_status pl_part_stats(pl_ctx *ctx, int64_t out[4])
+pl_status pl_part_stats(pl_ctx *ctx, int64_t out[6])
 {
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
     if (!c || !out) return PL_EINVAL;
-    for (int k = 0; k < 4; ++k) out[k] = c->stats[k];
+    for (int k = 0; k < 6; ++k) out[k] = c->stats[k];
     return PL_OK;
 }
 

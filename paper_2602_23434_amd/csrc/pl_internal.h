@@ -13,6 +13,8 @@ namespace pl {
 constexpr int kMaxCh = 8;            // rho, J0, J1, J2, F0, F1, F2, eng
 constexpr int kCellBits = 10;        // packed cell: 10 bits per dimension
 constexpr int kMaxN = 1 << kCellBits;
+constexpr int kRunLen = 4;           // particles per run of the run table (PL_ALGO_RUNS)
+constexpr int kRunsMaxTileCells = 1024;
 
 enum Channel { CH_RHO = 0, CH_J0 = 1, CH_F0 = 4, CH_ENG = 7 };
 
@@ -54,6 +56,7 @@ struct ItemDesc {
     void *w;
     void *fp[3];
     int32_t *tile_start;
+    int32_t *runs;           // run table (PL_ALGO_RUNS)
     // fields
     const double *E[3];
     const double *B[3];
@@ -89,6 +92,7 @@ struct Ctx {
     int block = 256;
     int lds_max = 65536;
     bool runs = false;               // tiled: contiguous per-thread particle runs (tune cache "runs 1")
+    int runs_block = 512;            // block size of the run-based kernels (init block or tune cache "runs_block")
 
     // device scratch
     ItemDesc *table = nullptr;       // max_items descriptors for non-graph calls
@@ -115,7 +119,8 @@ struct Ctx {
     GraphEntry graphs[kGraphs];
     uint64_t use_clock = 0;
 
-    int64_t stats[4] = {0, 0, 0, 0}; // launches, graph replays, graph captures, sorts
+    int64_t stats[6] = {0, 0, 0, 0, 0, 0}; // launches, graph replays, graph captures, sorts,
+                                           // run-kernel launches, run groups on the tiled kernel
 };
 
 // Kernel launchers (k_step.hip)
@@ -142,6 +147,7 @@ struct SortArgs {
     int esize[kMaxArrays];
     int narrays;
     int32_t *tile_start;
+    int32_t *runs;                   // nullable: run table to build (PL_ALGO_RUNS)
 };
 hipError_t launch_sort(Ctx *c, const SortArgs &a);
 

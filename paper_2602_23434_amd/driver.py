@@ -27,13 +27,15 @@ def _ptr(t):
 class Run:
     """One context plus the device arrays of every item of a workload."""
 
-    def __init__(self, wl, prec=B.PL_F64, algo=B.PL_ALGO_PLAIN, key_mode=B.PL_KEY_TILE, block=0,
+    def __init__(self, wl, prec=B.PL_F64, algo=B.PL_ALGO_PLAIN, key_mode=None, block=0,
                  tile=None, c=1.0, weights=True, ids=True, fp=False, eng=True, sort_buffers=True,
                  tune_cache=None, channels=None, device="cuda"):
         import torch
 
         self.torch = torch
         self.wl = wl
+        if key_mode is None:
+            key_mode = B.PL_KEY_TILE_CELL if algo == B.PL_ALGO_RUNS else B.PL_KEY_TILE
         self.prec = prec
         self.algo = algo
         self.dev = torch.device(device)
@@ -103,6 +105,9 @@ class Run:
                 extra = {
                     "fp": [torch.zeros(n, dtype=fdt, device=self.dev) for _ in range(3)] if fp else None,
                     "tile_start": torch.zeros(bx.n[0] * bx.n[1] * bx.n[2] + 1, dtype=torch.int32, device=self.dev),
+                    # run table: n entries + one count per tile (at most one tile per cell)
+                    "runs": (torch.zeros(n + bx.n[0] * bx.n[1] * bx.n[2] + 1, dtype=torch.int32, device=self.dev)
+                             if algo == B.PL_ALGO_RUNS else None),
                 }
                 self.parts.append({"sets": sets, **extra})
                 shape = (bx.n[2], bx.n[1], bx.n[0])
@@ -155,6 +160,7 @@ class Run:
             for a in range(3):
                 rec.p.fp[a] = _ptr(p["fp"][a])
         rec.p.tile_start = _ptr(p["tile_start"])
+        rec.p.runs = _ptr(p["runs"])
         f = self.fields[it.box]
         for a in range(3):
             if kind == B.PL_LORENTZ:
@@ -230,6 +236,8 @@ class Run:
                 continue
             out[k] = [t.cpu().numpy() for t in v] if isinstance(v, list) else v.cpu().numpy()
         out["tile_start"] = self.parts[i]["tile_start"].cpu().numpy()
+        if self.parts[i]["runs"] is not None:
+            out["runs"] = self.parts[i]["runs"].cpu().numpy()
         return out
 
     def moments(self, i):
@@ -239,6 +247,14 @@ class Run:
         for k, v in mo.items():
             out[k] = [t.cpu().numpy() for t in v] if isinstance(v, list) else v.cpu().numpy()
         return out
+
+    def zero_moments(self):
+        """Zero every item's moment grids on the context's stream."""
+        with self.torch.cuda.stream(self.stream):
+            for mo in self.moms:
+                for v in mo.values():
+                    for t in (v if isinstance(v, list) else [v]):
+                        t.zero_()
 
     def close(self):
         if self.ctx:

@@ -57,7 +57,7 @@ int main(void) {
   O(pl_init_desc, block) O(pl_init_desc, stream) O(pl_init_desc, tune_cache)
   S(pl_particles) O(pl_particles, cur) O(pl_particles, cell) O(pl_particles, x) O(pl_particles, u)
   O(pl_particles, w) O(pl_particles, id) O(pl_particles, fp) O(pl_particles, tile_start)
-  O(pl_particles, cell_start)
+  O(pl_particles, runs)
   S(pl_fields) O(pl_fields, B) O(pl_fields, vg)
   S(pl_moments) O(pl_moments, J) O(pl_moments, F) O(pl_moments, eng)
   S(pl_item) O(pl_item, p) O(pl_item, f) O(pl_item, m)
@@ -116,12 +116,24 @@ def _desc(**kw):
     dict(dx=(1.0, -1.0, 1.0)), dict(kind=9), dict(m=0.0), dict(kind=B.PL_DUST, t_stop=0.0),
     dict(ndim=2),          # 2D with n[2] = 8
     dict(nboxes=0),
+    dict(algo=2),                                   # run-based kernel needs the tile+cell key
+    dict(algo=2, key_mode=1, block=256),            # run-based block is 512 or 1024
+    dict(algo=2, key_mode=1, max_np=1 << 29),       # run entries hold the first index in 30 bits
 ])
 def test_init_rejects_bad_descriptions(lib, bad):
     d = _desc(**bad)
     ctx = C.c_void_p()
     st = lib.pl_part_init(C.byref(ctx), C.byref(d))
     assert st == B.PL_EINVAL
+    assert not ctx.value
+
+
+def test_runs_tile_limit(lib):
+    """The run table build keeps per-cell counts of one tile in LDS: at most
+    1024 cells per tile."""
+    d = _desc(algo=2, key_mode=1, n=(64, 64, 64), tile=(16, 16, 8))
+    ctx = C.c_void_p()
+    assert lib.pl_part_init(C.byref(ctx), C.byref(d)) == B.PL_EUNSUPPORTED
     assert not ctx.value
 
 
