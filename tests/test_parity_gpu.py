@@ -412,27 +412,75 @@ def test_invalid_items_rejected(mods):
 
 # ---------------------------------------------------------------- full size, bench configuration
 
-@pytest.mark.parametrize("path", ["f32_tiled", "f64_plain"])
+def _sampled_cells_check(oracle, wl, gm, steps, ncells=48, seed=12, margin=2.0):
+    """Deposits at sampled cells against the oracle: the particles whose
+    initial position lies within `margin` cells of a sampled cell (every
+    particle that can reach its stencil in `steps` steps at the workload's
+    speeds) are advanced by the oracle; the last step deposits.  Returns the
+    largest error per channel relative to the oracle's A_c at that cell."""
+    box = wl.boxes[0]
+    n = box.n[0]
+    rng = np.random.default_rng(seed)
+    cells = rng.integers(0, n, size=(ncells, 3))
+    it = wl.items[0].particles
+    x = it.x
+    mark = np.zeros((n, n, n), dtype=bool)
+    r = int(np.ceil(margin))
+    off = np.arange(-r, r + 1)
+    for c in cells:
+        mark[np.ix_((c[2] + off) % n, (c[1] + off) % n, (c[0] + off) % n)] = True
+    ci = np.floor(x).astype(np.int64) % n
+    near = mark[ci[2], ci[1], ci[0]]
+    xs = np.ascontiguousarray(x[:, near])
+    us = np.ascontiguousarray(it.u[:, near])
+    ws = np.ascontiguousarray(it.w[near])
+    sp = (oracle.LORENTZ, 1.0, 1.0, 0.0)
+    for _ in range(steps - 1):
+        oracle.step(3, box.n, oracle.TSC, sp, xs, us, ws, box.fields, wl.dt)
+    mom = oracle.new_moments(box.n, oracle.LORENTZ)
+    ab = oracle.new_moments(box.n, oracle.LORENTZ)
+    oracle.step(3, box.n, oracle.TSC, sp, xs, us, ws, box.fields, wl.dt, moments=mom, abs_moments=ab)
+    worst = {}
+    for name in ("rho", "J", "F"):
+        ref = mom[name] if name == "rho" else np.stack(mom[name])
+        scale = ab[name] if name == "rho" else np.stack(ab[name])
+        got = np.asarray(gm[name]) if name == "rho" else np.stack(gm[name])
+        e = 0.0
+        for c in cells:
+            idx = (..., c[2], c[1], c[0])
+            e = max(e, float((np.abs(got[idx] - ref[idx]) / np.maximum(scale[idx], 1e-300)).max()))
+        worst[name] = e
+    return worst
+
+
+@pytest.mark.parametrize("path", ["f32_runs", "f32_tiled", "f64_plain"])
 def test_fullsize_sampled(mods, path):
     """128^3 turbulent box, 2^24 particles, 20 steps, in the launch
-    configuration the benchmark times.  The oracle advances a sample of 2048
-    particles (a particle's update reads only the fields) and they are compared
-    per id; the deposit is checked through conservation: total charge equals
-    the particle count exactly, and the grid sums of J and F equal the
+    configuration the benchmark times (sorted paths re-sort every
+    SORT_EVERY steps).  The oracle advances a sample of 2048 particles (a
+    particle's update reads only the fields) and they are compared per id;
+    the deposit is compared at 48 sampled cells (the oracle advances every
+    particle that can reach them) and through conservation: total charge
+    equals the particle count, and the grid sums of J and F equal the
     particle-side sums."""
     oracle, driver, inputs, B = mods
     from paper_2602_23434_amd import benchcfg as BC
     say(f"[parity] full size 128^3, 2^24 particles, 20 steps, {path} (bench configuration)")
     wl = inputs.turbulent_box(n=BC.TURB_N, npart=BC.TURB_NP, steps=20)
-    cfg = BC.F32_TILED if path == "f32_tiled" else BC.F64_PLAIN
+    cfg = {"f32_runs": BC.F32_RUNS, "f32_tiled": BC.F32_TILED, "f64_plain": BC.F64_PLAIN}[path]
     run = driver.Run(wl, **cfg)
-    if cfg["algo"] == B.PL_ALGO_TILED:
-        run.sort()
+    sorted_path = cfg["algo"] != B.PL_ALGO_PLAIN
     for s in range(wl.steps):
+        if sorted_path and s % BC.SORT_EVERY == 0:
+            run.sort()
         fl = BC.STEP_FLAGS | (B.PL_SUMS if s == wl.steps - 1 else 0)
         run.step(flags=fl)
     assert run.sync() == B.PL_OK
+    if path == "f32_runs":
+        st = B.pl_part_stats(run.ctx)
+        assert st[4] > 0 and st[5] == 0, st
     gx, gu, gid, _ = run.state(0)
+    gm = run.moments(0)
     sums = run.sums()[0]
     run.close()
     rng = np.random.default_rng(11)
@@ -449,11 +497,16 @@ def test_fullsize_sampled(mods, path):
     dx = np.abs(_cmp.min_image(gxs - x, 128)).max()
     du = (np.sqrt(((gus - u) ** 2).sum(axis=0)) / np.maximum(np.sqrt((u * u).sum(axis=0)), 0.05)).max()
     say(f"  sampled max |dx| {dx:.3e} cells, max |du|/max(|u|,sigma) {du:.3e}")
-    if path == "f64_plain":
+    f64 = path == "f64_plain"
+    if f64:
         assert dx <= X_TOL and du <= U_TOL
     else:
         assert dx <= 2e-5 and du <= 2e-5
-    tol = 1e-12 if path == "f64_plain" else 1e-6
+    worst = _sampled_cells_check(oracle, wl, gm, wl.steps)
+    say("  sampled cells, max error / A_c: " + " ".join(f"{k} {v:.2e}" for k, v in worst.items()))
+    for k, v in worst.items():
+        assert v <= (M_TOL if f64 else 2e-5), k
+    tol = 1e-12 if f64 else 1e-6
     assert abs(sums[0] - BC.TURB_NP) <= tol * BC.TURB_NP
     for ch in range(1, 7):
         assert abs(sums[ch] - sums[8 + ch]) <= tol * max(abs(sums[8 + ch]), 1e-3 * BC.TURB_NP * 0.05), ch
