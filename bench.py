@@ -30,9 +30,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# the dominant kernel: run-based gather -> push -> deposit, float32 form, TSC,
-# 3D, charged particles, 512 threads, 8^3 tiles, channels rho + J + F
-KERNEL = "pl::k_runs<1, 2, 3, 0, 512, 1, 1>"
+
+
+def kernel_name(cfg, B):
+    """Name of the dominant kernel of a float32 configuration: the fused
+    gather -> push -> deposit kernel for TSC, 3D, charged particles, channels
+    rho + J + F (compile-time tile shape 8^3 or 8x8x4 when the tile is one)."""
+    tile = tuple(cfg["tile"])
+    if cfg["algo"] == B.PL_ALGO_RUNS:
+        ts = {(8, 8, 8): 1, (8, 8, 4): 2}.get(tile, 0)
+        return f"pl::k_runs<1, 2, 3, 0, {cfg['block'] if ts else 512}, {ts}, {1 if ts else 0}>"
+    ts = {(8, 8, 8): 1, (8, 8, 4): 2}.get(tile, 0)
+    return f"pl::k_step<1, 2, 3, true, 0, {ts}, {1 if ts else 0}>"
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_runs_f32_turbulent128_traffic.json")
 DIGEST_FILES = ("k_runs_impl.h", "k_runs_f32.hip", "k_step_impl.h", "pl_device.h", "pl_internal.h")
 
@@ -157,7 +167,9 @@ def main():
     from paper_2602_23434_amd import driver, inputs
 
     B.lib()
-    every = BC.SORT_EVERY if args.sort_every is None else args.sort_every
+    head_cfg, f64_cfg = BC.headline(), BC.f64_sorted()
+    every = head_cfg["sort_every"] if args.sort_every is None else args.sort_every
+    every64 = f64_cfg["sort_every"] if args.sort_every is None else args.sort_every
     t0 = time.perf_counter()
     wl = inputs.turbulent_box(n=BC.TURB_N, npart=BC.TURB_NP, steps=args.steps)
     log(f"[bench] inputs generated in {time.perf_counter() - t0:.1f} s")
@@ -165,12 +177,12 @@ def main():
     cells = BC.TURB_N ** 3
 
     results = {}
-    paths = [("f32_runs", BC.F32_RUNS, every, args.reps)]
+    paths = [("f32_runs", BC.run_kwargs(head_cfg), every, args.reps)]
     if not args.no_tiled:
         paths.append(("f32_tiled", BC.F32_TILED, every, args.reps))
     if not args.no_fp64:
         paths.append(("f64_plain", BC.F64_PLAIN, 0, 1))
-        paths.append(("f64_runs", BC.F64_RUNS, every, args.reps))
+        paths.append(("f64_runs", BC.run_kwargs(f64_cfg), every64, args.reps))
     for name, cfg, ev_every, reps in paths:
         log(f"[bench] path {name}: setup")
         run = driver.Run(wl, **cfg)
@@ -192,7 +204,7 @@ def main():
         torch.cuda.empty_cache()
 
     head = results["f32_runs"]
-    if head["stats"][4] == 0 or head["stats"][5] != 0:
+    if head_cfg["algo"] == B.PL_ALGO_RUNS and (head["stats"][4] == 0 or head["stats"][5] != 0):
         raise RuntimeError(f"the run-based kernel did not take the timed steps: stats {head['stats']}")
     achieved = head["alg_bytes"] / (head["kernel_ms"] * 1e-3) / 1e9
     traffic = None
@@ -219,12 +231,12 @@ def main():
                                f"{every} steps inside the timed loop, deposit rho+J+F (inputs of the float64 "
                                "128^3 configuration)",
                    "grid": [BC.TURB_N] * 3, "particles": npart, "dt": 0.05, "shape": "tsc",
-                   "tile": list(BC.F32_RUNS["tile"]), "block": BC.F32_RUNS["block"], "sort_key": "tile+cell",
+                   "tile": list(head_cfg["tile"]), "block": head_cfg["block"], "sort_key": "tile+cell",
                    "sort_every": every, "graph": not args.eager, "reps": args.reps,
                    "ms_per_step_min": head["ms_min"], "ms_per_step_max": head["ms_max"],
                    "sort_ms": head["sort_ms"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": KERNEL,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel_name(head_cfg, B),
                      "kernel_ms": head["kernel_ms"], "alg_bytes_per_launch": head["alg_bytes"]},
     }
     for name, key in (("f32_tiled", "fp32_tiled"), ("f64_plain", "fp64_plain"), ("f64_runs", "fp64_runs")):

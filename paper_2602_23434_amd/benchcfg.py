@@ -20,6 +20,41 @@ F32_RUNS = dict(prec=B.PL_F32_OFFSET, algo=B.PL_ALGO_RUNS, key_mode=B.PL_KEY_TIL
                 channels=CHANNELS, eng=False)
 F64_RUNS = dict(prec=B.PL_F64, algo=B.PL_ALGO_RUNS, key_mode=B.PL_KEY_TILE_CELL, tile=(8, 8, 4), block=512,
                 channels=CHANNELS, eng=False)
-# steps between sorts inside the timed loop (the autotuner's cadence choice
-# for this workload)
+# steps between sorts inside the timed loop when no tune file is present
 SORT_EVERY = 8
+
+
+def _tuned(cfg, prec):
+    """cfg with the autotuner's choice (tune_mi355x_*.txt next to this
+    module, written by `python -m paper_2602_23434_amd.tune`) applied:
+    algorithm, sort key, tile, block and sort cadence."""
+    import os
+
+    from . import tune
+    path = tune.tune_file(prec)
+    out = dict(cfg)
+    out["sort_every"] = SORT_EVERY
+    if not os.path.exists(path):
+        return out
+    t = tune.read_cache(path)
+    out["algo"] = int(t.get("algo", out["algo"]))
+    out["key_mode"] = int(t.get("key", out["key_mode"]))
+    out["tile"] = tuple(int(v) for v in t.get("tile", out["tile"]))
+    out["block"] = int(t.get("runs_block", t.get("block", out["block"])))
+    out["sort_every"] = int(t.get("sort_every", SORT_EVERY))
+    return out
+
+
+def headline():
+    """The float32 configuration the benchmark times (tuned when a tune file exists)."""
+    return _tuned(F32_RUNS, B.PL_F32_OFFSET)
+
+
+def f64_sorted():
+    """The sorted float64 configuration beside it (tuned when a tune file exists)."""
+    return _tuned(F64_RUNS, B.PL_F64)
+
+
+def run_kwargs(cfg):
+    """driver.Run keyword arguments of a configuration."""
+    return {k: v for k, v in cfg.items() if k != "sort_every"}

@@ -1,13 +1,16 @@
-"""Autotuner for the tiled step: tile shape, threads per block, sort key and
-sort cadence.
+"""Autotuner for the particle step: tile shape, threads per block and sort
+cadence of the run-based kernel (the tiled kernel with its rank key is timed
+beside it as a reference candidate).
 
-    python -m paper_2602_23434_amd.tune --out tune_cache.txt [--n 128 --ppc 8 --steps 8]
+    python -m paper_2602_23434_amd.tune [--f64] [--n 128 --ppc 8 --steps 16] [--out FILE]
 
 For every candidate it builds a context on a synthetic turbulent box of the
-requested size, sorts, and times `steps` fused steps with the sort repeated at
-the candidate cadence (the sort's cost is amortised into the per-step time).
-The winner is written as "key value" lines that pl_part_init reads (block,
-tile) and the Python driver reads (key, sort_every).
+requested size and times `steps` fused steps with the sort repeated at the
+candidate cadence, so the sort's cost is amortised into the per-step time
+exactly as in the benchmark.  The winner is written as "key value" lines:
+pl_part_init reads block, runs_block and tile; the Python side reads algo,
+key and sort_every.  Without --out the file is the package's tune file for
+the precision (tune_mi355x_f32.txt / tune_mi355x_f64.txt).
 """
 
 from __future__ import annotations
@@ -15,32 +18,40 @@ from __future__ import annotations
 import argparse
 import itertools
 import json
+import os
 import sys
 import time
 
 from . import binding as B
 from . import driver, inputs
 
-TILES = [(8, 8, 8), (8, 8, 4), (16, 8, 8), (8, 4, 4), (16, 8, 4)]
-BLOCKS = [256, 512]
-KEYS = [B.PL_KEY_TILE, B.PL_KEY_TILE_RANK]
-CADENCES = [1, 4, 0]          # 0 = sort once at setup only
+HERE = os.path.dirname(os.path.abspath(__file__))
+TILES = [(8, 8, 8), (8, 8, 4), (16, 8, 4), (8, 4, 4)]
+RUN_BLOCKS = [512, 1024]
+CADENCES = [4, 8, 16]
 CHANNELS = ["rho", "J0", "J1", "J2", "F0", "F1", "F2"]
 
 
-def time_candidate(wl, prec, tile, block, key, every, steps, torch):
-    run = driver.Run(wl, prec=prec, algo=B.PL_ALGO_TILED, tile=tile, block=block, key_mode=key,
-                     channels=CHANNELS, eng=False)
+def tune_file(prec):
+    return os.path.join(HERE, "tune_mi355x_f32.txt" if prec == B.PL_F32_OFFSET else "tune_mi355x_f64.txt")
+
+
+def time_candidate(wl, prec, algo, tile, block, key, every, steps, torch):
     try:
+        run = driver.Run(wl, prec=prec, algo=algo, tile=tile, block=block, key_mode=key, channels=CHANNELS,
+                         eng=False)
+    except B.PLError:
+        return None
+    try:
+        flags = B.PL_FUSE_DEPOSIT | B.PL_ZERO_FIRST | B.PL_GRAPH
         run.sort()
-        flags = B.PL_FUSE_DEPOSIT | B.PL_ZERO_FIRST
         run.step(flags=flags)
         run.sync()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(run.stream)
         for s in range(steps):
-            if every and s % every == every - 1:
+            if s % every == 0:
                 run.sort()
             run.step(flags=flags)
         e1.record(run.stream)
@@ -48,6 +59,10 @@ def time_candidate(wl, prec, tile, block, key, every, steps, torch):
         st = run.sync()
         if st != B.PL_OK:
             return None
+        if algo == B.PL_ALGO_RUNS:
+            stats = B.pl_part_stats(run.ctx)
+            if stats[5] != 0:          # LDS footprint too large: the tiled kernel ran
+                return None
         return e0.elapsed_time(e1) / steps
     except B.PLError:
         return None
@@ -55,28 +70,42 @@ def time_candidate(wl, prec, tile, block, key, every, steps, torch):
         run.close()
 
 
-def tune(n=128, ppc=8, steps=8, prec=B.PL_F32_OFFSET, log=print):
+def candidates(n, prec):
+    for tile, block, every in itertools.product(TILES, RUN_BLOCKS, CADENCES):
+        if any(n % t for t in tile):
+            continue
+        yield B.PL_ALGO_RUNS, tile, block, B.PL_KEY_TILE_CELL, every
+    # reference: the tiled kernel with the rank-interleaved key
+    tile = (8, 8, 8) if prec == B.PL_F32_OFFSET else (8, 8, 4)
+    for every in CADENCES:
+        yield B.PL_ALGO_TILED, tile, 512, B.PL_KEY_TILE_RANK, every
+
+
+def tune(n=128, ppc=8, steps=16, prec=B.PL_F32_OFFSET, log=print):
     import torch
     wl = inputs.turbulent_box(n=n, npart=ppc * n ** 3, steps=steps)
     best = None
     results = []
-    for tile, block, key, every in itertools.product(TILES, BLOCKS, KEYS, CADENCES):
-        if any(n % t for t in tile):
-            continue
-        ms = time_candidate(wl, prec, tile, block, key, every, steps, torch)
-        results.append({"tile": tile, "block": block, "key": key, "sort_every": every, "ms": ms})
-        log(f"[tune] tile {tile} block {block} key {key} sort_every {every}: "
+    for algo, tile, block, key, every in candidates(n, prec):
+        ms = time_candidate(wl, prec, algo, tile, block, key, every, steps, torch)
+        results.append({"algo": algo, "tile": tile, "block": block, "key": key, "sort_every": every, "ms": ms})
+        log(f"[tune] algo {algo} tile {tile} block {block} key {key} sort_every {every}: "
             f"{'unsupported' if ms is None else f'{ms:.3f} ms/step'}")
         if ms is not None and (best is None or ms < best["ms"]):
             best = results[-1]
     return best, results
 
 
-def write_cache(path, best):
+def write_cache(path, best, n, ppc):
     with open(path, "w") as fh:
-        fh.write(f"block {best['block']}\n")
-        fh.write("tile {} {} {}\n".format(*best["tile"]))
+        fh.write(f"# autotuned on MI355X: turbulent {n}^3 box, {ppc} particles per cell\n")
+        fh.write(f"algo {best['algo']}\n")
         fh.write(f"key {best['key']}\n")
+        if best["algo"] == B.PL_ALGO_RUNS:
+            fh.write(f"runs_block {best['block']}\n")
+        else:
+            fh.write(f"block {best['block']}\n")
+        fh.write("tile {} {} {}\n".format(*best["tile"]))
         fh.write(f"sort_every {best['sort_every']}\n")
         fh.write(f"ms_per_step {best['ms']:.4f}\n")
 
@@ -86,7 +115,7 @@ def read_cache(path):
     with open(path) as fh:
         for line in fh:
             parts = line.split()
-            if not parts:
+            if not parts or parts[0].startswith("#"):
                 continue
             vals = [float(v) if "." in v else int(v) for v in parts[1:]]
             out[parts[0]] = vals[0] if len(vals) == 1 else tuple(vals)
@@ -95,16 +124,16 @@ def read_cache(path):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default="tune_cache.txt")
+    ap.add_argument("--out", default=None)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--ppc", type=int, default=8)
-    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--f64", action="store_true")
     a = ap.parse_args()
+    prec = B.PL_F64 if a.f64 else B.PL_F32_OFFSET
     t0 = time.perf_counter()
-    best, results = tune(a.n, a.ppc, a.steps, B.PL_F64 if a.f64 else B.PL_F32_OFFSET,
-                         log=lambda m: print(m, file=sys.stderr, flush=True))
-    write_cache(a.out, best)
+    best, results = tune(a.n, a.ppc, a.steps, prec, log=lambda m: print(m, file=sys.stderr, flush=True))
+    write_cache(a.out or tune_file(prec), best, a.n, a.ppc)
     print(json.dumps({"best": best, "seconds": time.perf_counter() - t0}))
 
 

@@ -467,11 +467,12 @@ def test_fullsize_sampled(mods, path):
     from paper_2602_23434_amd import benchcfg as BC
     say(f"[parity] full size 128^3, 2^24 particles, 20 steps, {path} (bench configuration)")
     wl = inputs.turbulent_box(n=BC.TURB_N, npart=BC.TURB_NP, steps=20)
-    cfg = {"f32_runs": BC.F32_RUNS, "f32_tiled": BC.F32_TILED, "f64_plain": BC.F64_PLAIN}[path]
-    run = driver.Run(wl, **cfg)
+    cfg = {"f32_runs": BC.headline(), "f32_tiled": dict(BC.F32_TILED, sort_every=BC.SORT_EVERY),
+           "f64_plain": BC.F64_PLAIN}[path]
+    run = driver.Run(wl, **BC.run_kwargs(cfg))
     sorted_path = cfg["algo"] != B.PL_ALGO_PLAIN
     for s in range(wl.steps):
-        if sorted_path and s % BC.SORT_EVERY == 0:
+        if sorted_path and s % cfg["sort_every"] == 0:
             run.sort()
         fl = BC.STEP_FLAGS | (B.PL_SUMS if s == wl.steps - 1 else 0)
         run.step(flags=fl)
