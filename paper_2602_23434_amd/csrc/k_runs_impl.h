@@ -643,7 +643,7 @@ __global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(RB / 256, RB
             __syncthreads();
         }
 
-        const int32_t *runs = I.runs + pbeg;
+        const gptr<const int32_t> runs = (gptr<const int32_t>)(I.runs + pbeg);
         for (int r = threadIdx.x; r < nruns; r += blockDim.x) {
             const int e = runs[r];
             int start = e >> 2;

@@ -73,13 +73,13 @@ template <int PREC> struct UnitC {
     R h, inv_c2, c2, q, m, wdef, inv_dt, decay, one_m_decay;
     R dtdx[3];
     double inv_dv;
-    uint32_t *cell;
-    R *x[3];
-    R *u[3];
-    const R *w;
-    R *fp[3];
-    const double *gf[6];
-    double *M[kMaxCh];
+    gptr<uint32_t> cell;
+    gptr<R> x[3];
+    gptr<R> u[3];
+    gptr<const R> w;
+    gptr<R> fp[3];
+    gptr<const double> gf[6];
+    gptr<double> M[kMaxCh];
     int soff[kMaxCh];      // offset of each active channel in the LDS deposit tile, -1 if inactive
 };
 
@@ -90,9 +90,9 @@ __device__ __forceinline__ void load_unit(const ItemDesc &I, UnitC<PREC> &U, int
     for (int a = 0; a < 3; ++a) {
         U.n[a] = I.n[a];
         U.dtdx[a] = (R)I.dtdx[a];
-        U.x[a] = (R *)I.x[a];
-        U.u[a] = (R *)I.u[a];
-        U.fp[a] = (R *)I.fp[a];
+        U.x[a] = (gptr<R>)I.x[a];
+        U.u[a] = (gptr<R>)I.u[a];
+        U.fp[a] = (gptr<R>)I.fp[a];
     }
     U.np = I.np;
     U.kind = I.kind;
@@ -106,21 +106,21 @@ __device__ __forceinline__ void load_unit(const ItemDesc &I, UnitC<PREC> &U, int
     U.decay = (R)I.decay;
     U.one_m_decay = (R)I.one_m_decay;
     U.inv_dv = I.inv_dv;
-    U.cell = I.cell;
-    U.w = (const R *)I.w;
+    U.cell = (gptr<uint32_t>)I.cell;
+    U.w = (gptr<const R>)I.w;
     if (I.kind == PL_LORENTZ) {
         for (int a = 0; a < 3; ++a) {
-            U.gf[a] = I.E[a];
-            U.gf[3 + a] = I.B[a];
+            U.gf[a] = (gptr<const double>)I.E[a];
+            U.gf[3 + a] = (gptr<const double>)I.B[a];
         }
     } else {
         for (int a = 0; a < 3; ++a) {
-            U.gf[a] = I.vg[a];
+            U.gf[a] = (gptr<const double>)I.vg[a];
             U.gf[3 + a] = nullptr;
         }
     }
     for (int ch = 0; ch < kMaxCh; ++ch) {
-        U.M[ch] = I.M[ch];
+        U.M[ch] = (gptr<double>)I.M[ch];
         U.soff[ch] = I.slot[ch] >= 0 ? I.slot[ch] * L : -1;
     }
 }

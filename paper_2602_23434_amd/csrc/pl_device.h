@@ -10,6 +10,13 @@
 namespace pl {
 
 template <int PREC> struct RealOf { using T = double; };
+
+// Pointer into global memory.  Pointers read from the item table are generic
+// (flat) pointers; loads and stores through flat pointers also count against
+// the LDS wait counter, so every wait for an LDS read would wait for
+// outstanding HBM loads as well.  Per-unit pointers are converted to this
+// type once, and every particle, field and moment access goes through it.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
 template <> struct RealOf<PL_F32_OFFSET> { using T = float; };
 
 // Sum over the 64 lanes of a wave.
@@ -25,6 +32,11 @@ __device__ __forceinline__ void global_add(double *p, double v)
 {
     __hip_atomic_fetch_add((__attribute__((address_space(1))) double *)p, v, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void global_add(gptr<double> p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ int wrap_cell(int i, int n)
@@ -107,7 +119,7 @@ template <int DIM> struct Pos<PL_F64, DIM> {
     {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            x[a] = a < DIM ? wrap(((const double *)it.x[a])[p], it.n[a], err) : 0.0;
+            x[a] = a < DIM ? wrap((double)it.x[a][p], it.n[a], err) : 0.0;
             c[a] = 0;
             d[a] = 0.0;
         }
@@ -118,7 +130,7 @@ template <int DIM> struct Pos<PL_F64, DIM> {
     __device__ __forceinline__ void store(const S &it, int p) const
     {
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) ((double *)it.x[a])[p] = x[a];
+        for (int a = 0; a < DIM; ++a) it.x[a][p] = x[a];
     }
 
     // Move by disp cells per dimension and wrap periodically.
@@ -151,7 +163,7 @@ template <int DIM> struct Pos<PL_F32_OFFSET, DIM> {
             if (a < DIM) {
                 c[a] = ijk[a];
                 if (c[a] >= it.n[a]) { err |= ERR_NONFINITE; c[a] %= it.n[a]; }
-                float o = ((const float *)it.x[a])[p];
+                float o = it.x[a][p];
                 if (!(o >= -0.5f && o < 0.5f)) { err |= ERR_NONFINITE; o = 0.0f; }
                 d[a] = o;
             } else {
@@ -166,7 +178,7 @@ template <int DIM> struct Pos<PL_F32_OFFSET, DIM> {
     {
         it.cell[p] = pack_cell(c[0], DIM > 1 ? c[1] : 0, DIM > 2 ? c[2] : 0);
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) ((float *)it.x[a])[p] = d[a];
+        for (int a = 0; a < DIM; ++a) it.x[a][p] = d[a];
     }
 
     // Offset update in float32; when the particle leaves its cell the new
