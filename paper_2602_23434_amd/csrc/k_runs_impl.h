@@ -27,7 +27,9 @@
 
 namespace pl {
 
-constexpr int kGQ = 256;                     // particles queued for the single-particle path
+// Capacity of the queue of particles that need the HBM gather: with a
+// two-cell field halo only particles two cells out of their tile land there.
+__host__ __device__ constexpr int gq_cap(int hf) { return hf == 2 ? 64 : 256; }
 
 template <int PREC> struct RunsQ { static constexpr int DQ = PREC == PL_F32_OFFSET ? 256 : 128; };
 
@@ -79,24 +81,33 @@ __device__ __forceinline__ int wrap_any(int i, int n)
     return r < 0 ? r + n : r;
 }
 
-// Geometry of one tile: field tile with a one-cell halo, deposit tile with a
-// two-cell halo.
+// Geometry of one tile: field tile with an hf-cell halo (1 or 2), deposit
+// tile with a two-cell halo.
 struct RunGeo {
     int lo[3], T[3];
+    int hf;
     int fx, fxy, Lf;
     int dx, dxy, Ld;
 };
 
 // LDS index (field tile) of stencil point (-1,-1,-1) of a particle in cell c,
-// when the whole stencil lies in the field tile (c inside the tile).
+// when the whole stencil lies in the field tile (c at most hf - 1 cells
+// outside the tile, periodically).
 template <int DIM>
-__device__ __forceinline__ bool field_base(const RunGeo &g, const int c[3], int &base)
+__device__ __forceinline__ bool field_base(const RunGeo &g, const int n[3], const int c[3], int &base)
 {
-    int l0 = c[0] - g.lo[0], l1 = DIM >= 2 ? c[1] - g.lo[1] : 0, l2 = DIM >= 3 ? c[2] - g.lo[2] : 0;
-    bool ok = (unsigned)l0 < (unsigned)g.T[0];
-    if (DIM >= 2) ok = ok && (unsigned)l1 < (unsigned)g.T[1];
-    if (DIM >= 3) ok = ok && (unsigned)l2 < (unsigned)g.T[2];
-    base = l0 + l1 * g.fx + l2 * g.fxy;
+    bool ok = true;
+    int l[3] = {0, 0, 0};
+    const int h = g.hf - 1;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        int v = c[a] - g.lo[a];
+        if (v < -h) v += n[a];
+        else if (v > g.T[a] - 1 + h) v -= n[a];
+        ok = ok && v >= -h && v <= g.T[a] - 1 + h;
+        l[a] = v + h;
+    }
+    base = l[0] + (DIM >= 2 ? l[1] * g.fx : 0) + (DIM >= 3 ? l[2] * g.fxy : 0);
     return ok;
 }
 
@@ -280,7 +291,7 @@ __device__ __forceinline__ void particle_single(const UnitC<PREC> &U, const RunG
     stencil_weights<PREC, SHAPE, DIM>(d0, wx, wy, wz);
     R F[NC];
     int fb = 0;
-    if (field_base<DIM>(G, pos.c, fb)) {
+    if (field_base<DIM>(G, U.n, pos.c, fb)) {
         gather_rec<PREC, DIM, KIND>(G, S.lds_f, fb, wx, wy, wz, F);
     } else {
         gather<PREC, DIM, NC>(U, nullptr, 0, false, 0, 0, 0, pos.c, wx, wy, wz, F);
@@ -482,26 +493,49 @@ __device__ __forceinline__ void batch_body(const UnitC<PREC> &U, const RunGeo &G
     if (any_dco) batch_deposit<PREC, SHAPE, DIM, CHS, KR>(U, G, S, db, pos, mu, dco);
 }
 
-// One run: batches of KR particles of one cell.
-template <int PREC, int SHAPE, int DIM, int KIND, int CHS, int KR>
-__device__ __forceinline__ void run_batch(const UnitC<PREC> &U, const RunGeo &G, const RunShared<PREC> &S, int start,
-                                          int len, bool do_sums, int &err)
+// Stored state of one batch (up to KR consecutive particles), fetched from
+// HBM one batch ahead of its use so the loads overlap the previous batch.
+template <int PREC, int DIM, int KR> struct BatchRaw {
+    using R = typename RealOf<PREC>::T;
+    typename Pos<PREC, DIM>::Raw pr[KR];
+    R u[KR][3], w[KR];
+    int start, len;
+};
+
+template <int PREC, int DIM, int KR>
+__device__ __forceinline__ void fetch_batch(const UnitC<PREC> &U, int start, int len, BatchRaw<PREC, DIM, KR> &B)
 {
     using R = typename RealOf<PREC>::T;
-    Pos<PREC, DIM> pos[KR];
-    R u[KR][3], w[KR];
-    pos[0].load(U, start, err);
+    B.start = start;
+    B.len = len;
 #pragma unroll
     for (int j = 0; j < KR; ++j) {
         const int p = start + j;
-        if (j > 0) {
-            if (j < len) pos[j].load(U, p, err);
-            else pos[j] = pos[0];
-        }
         const bool in = j < len;
+        if (in) Pos<PREC, DIM>::fetch(U, p, B.pr[j]);
+        else B.pr[j] = B.pr[0];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) u[j][a] = in ? U.u[a][p] : R(0);
-        w[j] = in ? (U.w ? U.w[p] : U.wdef) : R(0);
+        for (int a = 0; a < 3; ++a) B.u[j][a] = in ? U.u[a][p] : R(0);
+        B.w[j] = in ? (U.w ? U.w[p] : U.wdef) : R(0);
+    }
+}
+
+// One batch of up to KR particles of one run.
+template <int PREC, int SHAPE, int DIM, int KIND, int CHS, int KR>
+__device__ __forceinline__ void run_batch(const UnitC<PREC> &U, const RunGeo &G, const RunShared<PREC> &S,
+                                          const BatchRaw<PREC, DIM, KR> &Bt, bool do_sums, int &err)
+{
+    using R = typename RealOf<PREC>::T;
+    const int start = Bt.start, len = Bt.len;
+    Pos<PREC, DIM> pos[KR];
+    R u[KR][3], w[KR];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        if (j < len) pos[j].set(Bt.pr[j], U, err);
+        else pos[j] = pos[0];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[j][a] = Bt.u[j][a];
+        w[j] = Bt.w[j];
     }
     // every particle whose stencil lies in the LDS field tile is gathered in
     // the batch from its own cell (lanes read distinct records anyway)
@@ -509,7 +543,7 @@ __device__ __forceinline__ void run_batch(const UnitC<PREC> &U, const RunGeo &G,
     bool co[KR];
 #pragma unroll
     for (int j = 0; j < KR; ++j) {
-        co[j] = field_base<DIM>(G, pos[j].c, fb[j]) && j < len;
+        co[j] = field_base<DIM>(G, U.n, pos[j].c, fb[j]) && j < len;
         if (!co[j]) fb[j] = 0;       // computed but unused: keep its reads inside the field tile
     }
     // particles outside the tile: queue for the single-particle path (when
@@ -519,7 +553,7 @@ __device__ __forceinline__ void run_batch(const UnitC<PREC> &U, const RunGeo &G,
     for (int j = 0; j < KR; ++j) {
         if (j < len && !co[j]) {
             int q = atomicAdd(&S.ctl[1], 1);
-            if (q < kGQ) S.gq[q] = start + j;
+            if (q < gq_cap(G.hf)) S.gq[q] = start + j;
             else ovf_g |= 1u << j;
         }
     }
@@ -539,14 +573,14 @@ __device__ __forceinline__ void run_batch(const UnitC<PREC> &U, const RunGeo &G,
 __host__ __device__ inline size_t runs_section(size_t b) { return (b + 15) & ~(size_t)15; }
 
 template <int PREC, int KIND>
-__host__ __device__ inline size_t runs_lds_bytes(int Lf, int Ld, int nslot, size_t offs[6])
+__host__ __device__ inline size_t runs_lds_bytes(int Lf, int Ld, int nslot, int hf, size_t offs[6])
 {
     using R = typename RealOf<PREC>::T;
     constexpr int DQ = RunsQ<PREC>::DQ;
     size_t o = 0;
     offs[0] = o; o += runs_section((size_t)Lf * FieldRec<PREC, KIND>::FS * sizeof(R));
     offs[1] = o; o += runs_section((size_t)Ld * nslot * sizeof(double));
-    offs[2] = o; o += runs_section((size_t)kGQ * sizeof(int));
+    offs[2] = o; o += runs_section((size_t)gq_cap(hf) * sizeof(int));
     offs[3] = o; o += runs_section((size_t)DQ * sizeof(uint32_t));
     offs[4] = o; o += runs_section((size_t)DQ * (3 + nslot) * sizeof(R));
     offs[5] = o; o += 8 * sizeof(double);
@@ -586,9 +620,10 @@ __global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(RB / 256, RB
             G.lo[1] = ty * G.T[1];
             G.lo[2] = tz * G.T[2];
         }
-        G.fx = G.T[0] + 2;
-        G.fxy = G.fx * (G.T[1] + 2);
-        G.Lf = G.fxy * (DIM >= 3 ? G.T[2] + 2 : 1);
+        G.hf = (flags & SF_FHALO2) ? 2 : 1;
+        G.fx = G.T[0] + 2 * G.hf;
+        G.fxy = G.fx * (G.T[1] + 2 * G.hf);
+        G.Lf = G.fxy * (DIM >= 3 ? G.T[2] + 2 * G.hf : 1);
         G.dx = G.T[0] + 4;
         G.dxy = G.dx * (G.T[1] + 4);
         G.Ld = G.dxy * (DIM >= 3 ? G.T[2] + 4 : 1);
@@ -601,7 +636,7 @@ __global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(RB / 256, RB
         load_unit<PREC>(I, U, G.Ld);
         const int nslot = I.nslot;
         size_t offs[6];
-        runs_lds_bytes<PREC, KIND>(G.Lf, G.Ld, nslot, offs);
+        runs_lds_bytes<PREC, KIND>(G.Lf, G.Ld, nslot, G.hf, offs);
         RunShared<PREC> S;
         R *lds_f = reinterpret_cast<R *>(smem_raw + offs[0]);
         S.lds_f = lds_f;
@@ -613,16 +648,16 @@ __global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(RB / 256, RB
         S.ctl = ctl;
         S.sums = reinterpret_cast<double *>(smem_raw + offs[5]);
 
-        // stage the field records (one-cell halo) and clear the deposit tile
+        // stage the field records (hf-cell halo) and clear the deposit tile
         {
-            const int Ly = G.T[1] + 2;
+            const int Ly = G.T[1] + 2 * G.hf;
             for (int e = threadIdx.x; e < G.Lf; e += blockDim.x) {
                 int lx = e % G.fx;
                 int ly = (e / G.fx) % Ly;
                 int lz = e / G.fxy;
-                int gx = wrap_any(G.lo[0] + lx - 1, U.n[0]);
-                int gy = DIM >= 2 ? wrap_any(G.lo[1] + ly - 1, U.n[1]) : 0;
-                int gz = DIM >= 3 ? wrap_any(G.lo[2] + lz - 1, U.n[2]) : 0;
+                int gx = wrap_any(G.lo[0] + lx - G.hf, U.n[0]);
+                int gy = DIM >= 2 ? wrap_any(G.lo[1] + ly - G.hf, U.n[1]) : 0;
+                int gz = DIM >= 3 ? wrap_any(G.lo[2] + lz - G.hf, U.n[2]) : 0;
                 long gc = gx + (long)U.n[0] * (gy + (long)U.n[1] * gz);
 #pragma unroll
                 for (int q = 0; q < NC; ++q) lds_f[FR::at(e, q, G.Lf)] = (R)U.gf[q][gc];
@@ -643,18 +678,43 @@ __global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(RB / 256, RB
             __syncthreads();
         }
 
+        // this thread's runs r = tid, tid + blockDim, ..., each cut into
+        // batches of KR; the next batch is fetched before the current one runs
         const gptr<const int32_t> runs = (gptr<const int32_t>)(I.runs + pbeg);
-        for (int r = threadIdx.x; r < nruns; r += blockDim.x) {
+        auto run_span = [&](int r, int &rs, int &rl) {
             const int e = runs[r];
-            int start = e >> 2;
-            int len = (e & 3) + 1;
-            start = min(max(start, pbeg), pend - 1);
-            len = min(len, pend - start);
-            for (int b = 0; b < len; b += KR)
-                run_batch<PREC, SHAPE, DIM, KIND, CHS, KR>(U, G, S, start + b, min(KR, len - b), do_sums, err);
+            rs = min(max(e >> 2, pbeg), pend - 1);
+            rl = min((e & 3) + 1, pend - rs);
+        };
+        {
+            int r = threadIdx.x, b = 0, rs = 0, rl = 0;
+            bool have = r < nruns;
+            BatchRaw<PREC, DIM, KR> cur;
+            if (have) {
+                run_span(r, rs, rl);
+                fetch_batch<PREC, DIM, KR>(U, rs, min(KR, rl), cur);
+            }
+            while (have) {
+                int nr = r, nb = b + KR, nrs = rs, nrl = rl;
+                if (nb >= rl) {
+                    nr = r + blockDim.x;
+                    nb = 0;
+                    if (nr < nruns) run_span(nr, nrs, nrl);
+                }
+                const bool nhave = nr < nruns;
+                BatchRaw<PREC, DIM, KR> nxt;
+                if (nhave) fetch_batch<PREC, DIM, KR>(U, nrs + nb, min(KR, nrl - nb), nxt);
+                run_batch<PREC, SHAPE, DIM, KIND, CHS, KR>(U, G, S, cur, do_sums, err);
+                cur = nxt;
+                r = nr;
+                b = nb;
+                rs = nrs;
+                rl = nrl;
+                have = nhave;
+            }
         }
         __syncthreads();
-        const int ng = min(ctl[1], kGQ);
+        const int ng = min(ctl[1], gq_cap(G.hf));
         for (int i = threadIdx.x; i < ng; i += blockDim.x)
             particle_single<PREC, SHAPE, DIM, KIND, CHS>(U, G, S, S.gq[i], do_sums, err);
         const int nd = min(ctl[2], RunsQ<PREC>::DQ);
@@ -742,18 +802,28 @@ hipError_t launch_runs_impl(Ctx *c, const ItemDesc *table, const ItemDesc *host,
     const int rb = (ts != 0 && c->runs_block == 1024) ? 1024 : 512;
     StepKernel k = pick_runs<PREC>(c->d.shape, c->d.ndim, kind, rb, ts, chs);
     if (!k) return hipErrorInvalidConfiguration;
-    size_t lds = 0;
-    for (int i = 0; i < nitems; ++i) {
-        const ItemDesc &it = host[i];
-        const int d3 = c->d.ndim >= 3;
-        int Lf = (it.tile[0] + 2) * (it.tile[1] + 2) * (d3 ? it.tile[2] + 2 : 1);
-        int Ld = (it.tile[0] + 4) * (it.tile[1] + 4) * (d3 ? it.tile[2] + 4 : 1);
-        size_t offs[6];
-        size_t b = kind == PL_LORENTZ ? runs_lds_bytes<PREC, PL_LORENTZ>(Lf, Ld, it.nslot, offs)
-                                      : runs_lds_bytes<PREC, PL_DUST>(Lf, Ld, it.nslot, offs);
-        lds = std::max(lds, b);
+    // LDS of the group: a two-cell field halo when it fits, else one cell
+    auto group_lds = [&](int hf) {
+        size_t lds = 0;
+        for (int i = 0; i < nitems; ++i) {
+            const ItemDesc &it = host[i];
+            const int d3 = c->d.ndim >= 3;
+            int Lf = (it.tile[0] + 2 * hf) * (it.tile[1] + 2 * hf) * (d3 ? it.tile[2] + 2 * hf : 1);
+            int Ld = (it.tile[0] + 4) * (it.tile[1] + 4) * (d3 ? it.tile[2] + 4 : 1);
+            size_t offs[6];
+            size_t b = kind == PL_LORENTZ ? runs_lds_bytes<PREC, PL_LORENTZ>(Lf, Ld, it.nslot, hf, offs)
+                                          : runs_lds_bytes<PREC, PL_DUST>(Lf, Ld, it.nslot, hf, offs);
+            lds = std::max(lds, b);
+        }
+        return lds;
+    };
+    size_t lds = group_lds(2);
+    if (lds <= (size_t)c->lds_max) {
+        sf |= SF_FHALO2;
+    } else {
+        lds = group_lds(1);
+        if (lds > (size_t)c->lds_max) return hipErrorInvalidConfiguration;
     }
-    if (lds > (size_t)c->lds_max) return hipErrorInvalidConfiguration;
     int grid = std::min(total_units, resident_blocks(c, k, rb, lds));
     hipLaunchKernelGGL(k, dim3(grid), dim3(rb), lds, c->stream, table, nitems, total_units, counter, c->errflags, sf,
                        (int)lds);

@@ -114,16 +114,36 @@ template <int DIM> struct Pos<PL_F64, DIM> {
         return v;
     }
 
+    // Stored form of one particle's position (fetched ahead of use).
+    struct Raw {
+        double x[3];
+    };
+
     template <class S>
-    __device__ __forceinline__ void load(const S &it, int p, int &err)
+    __device__ __forceinline__ static void fetch(const S &it, int p, Raw &r)
+    {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) r.x[a] = a < DIM ? (double)it.x[a][p] : 0.0;
+    }
+
+    template <class S>
+    __device__ __forceinline__ void set(const Raw &r, const S &it, int &err)
     {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            x[a] = a < DIM ? wrap((double)it.x[a][p], it.n[a], err) : 0.0;
+            x[a] = a < DIM ? wrap(r.x[a], it.n[a], err) : 0.0;
             c[a] = 0;
             d[a] = 0.0;
         }
         locate();
+    }
+
+    template <class S>
+    __device__ __forceinline__ void load(const S &it, int p, int &err)
+    {
+        Raw r;
+        fetch(it, p, r);
+        set(r, it, err);
     }
 
     template <class S>
@@ -152,18 +172,31 @@ template <int DIM> struct Pos<PL_F32_OFFSET, DIM> {
 
     __device__ __forceinline__ void locate() {}
 
+    // Stored form of one particle's position (fetched ahead of use).
+    struct Raw {
+        uint32_t cell;
+        float o[3];
+    };
+
     template <class S>
-    __device__ __forceinline__ void load(const S &it, int p, int &err)
+    __device__ __forceinline__ static void fetch(const S &it, int p, Raw &r)
     {
-        uint32_t pc = it.cell[p];
+        r.cell = it.cell[p];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) r.o[a] = a < DIM ? (float)it.x[a][p] : 0.0f;
+    }
+
+    template <class S>
+    __device__ __forceinline__ void set(const Raw &r, const S &it, int &err)
+    {
         int ijk[3];
-        unpack_cell(pc, ijk[0], ijk[1], ijk[2]);
+        unpack_cell(r.cell, ijk[0], ijk[1], ijk[2]);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             if (a < DIM) {
                 c[a] = ijk[a];
                 if (c[a] >= it.n[a]) { err |= ERR_NONFINITE; c[a] %= it.n[a]; }
-                float o = it.x[a][p];
+                float o = r.o[a];
                 if (!(o >= -0.5f && o < 0.5f)) { err |= ERR_NONFINITE; o = 0.0f; }
                 d[a] = o;
             } else {
@@ -171,6 +204,14 @@ template <int DIM> struct Pos<PL_F32_OFFSET, DIM> {
                 d[a] = 0.0f;
             }
         }
+    }
+
+    template <class S>
+    __device__ __forceinline__ void load(const S &it, int p, int &err)
+    {
+        Raw r;
+        fetch(it, p, r);
+        set(r, it, err);
     }
 
     template <class S>

@@ -27,6 +27,7 @@ enum StepFlag : unsigned {
     SF_DEPOSIT = 2u,    // deposit moments
     SF_SUMS = 4u,       // particle-side conservation sums
     SF_RUNS = 8u,       // tiled: each thread takes a contiguous run of the tile's particles
+    SF_FHALO2 = 16u,    // run-based: the LDS field tile carries a two-cell halo
 };
 
 // Everything a kernel needs to know about one item of a call.  Built on the
