@@ -2,7 +2,7 @@
 cadence of the run-based kernel (the tiled kernel with its rank key is timed
 beside it as a reference candidate).
 
-    python -m paper_2602_23434_amd.tune [--f64] [--n 128 --ppc 8 --steps 16] [--out FILE]
+    python -m paper_2602_23434_amd.tune [--f64] [--n 128 --ppc 8 --steps 32] [--out FILE]
 
 For every candidate it builds a context on a synthetic turbulent box of the
 requested size and times `steps` fused steps with the sort repeated at the
@@ -28,7 +28,7 @@ from . import driver, inputs
 HERE = os.path.dirname(os.path.abspath(__file__))
 TILES = [(8, 8, 8), (8, 8, 4), (16, 8, 4), (8, 4, 4)]
 RUN_BLOCKS = [512, 1024]
-CADENCES = [4, 8, 16]
+CADENCES = [8, 16, 32]
 CHANNELS = ["rho", "J0", "J1", "J2", "F0", "F1", "F2"]
 
 
@@ -81,7 +81,7 @@ def candidates(n, prec):
         yield B.PL_ALGO_TILED, tile, 512, B.PL_KEY_TILE_RANK, every
 
 
-def tune(n=128, ppc=8, steps=16, prec=B.PL_F32_OFFSET, log=print):
+def tune(n=128, ppc=8, steps=32, prec=B.PL_F32_OFFSET, log=print):
     import torch
     wl = inputs.turbulent_box(n=n, npart=ppc * n ** 3, steps=steps)
     best = None
@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--ppc", type=int, default=8)
-    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=32)
     ap.add_argument("--f64", action="store_true")
     a = ap.parse_args()
     prec = B.PL_F64 if a.f64 else B.PL_F32_OFFSET
