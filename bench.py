@@ -114,6 +114,51 @@ def time_path(run, steps, warmup, reps, every, graph, torch, B):
             "kernel_ms": sum(kern) / len(kern), "sort_ms": (sum(sorts) / len(sorts)) if sorts else 0.0}
 
 
+def time_workload(wl, cfg, steps, every, torch, B, driver):
+    """Whole-step time of a multi-item workload (all items in one call per
+    step: one persistent launch per species kind), sort every `every` steps."""
+    run = driver.Run(wl, **cfg)
+    try:
+        run.sort()
+        run.sync()
+        total = sum(it.particles.n for it in wl.items)
+        timed_loop(run, 2, every, True, torch, B)
+        ms, kern, sorts = timed_loop(run, steps, every, True, torch, B)
+        stats = B.pl_part_stats(run.ctx)
+        return {"value": total * steps / (ms * 1e-3), "unit": "particle-updates/s", "particles": total,
+                "ms_per_step": ms / steps, "kernel_ms": sum(kern) / len(kern),
+                "sort_ms": (sum(sorts) / len(sorts)) if sorts else 0.0, "sort_every": every, "steps": steps,
+                "run_kernel_launches": stats[4], "tiled_fallback_groups": stats[5]}
+    finally:
+        run.close()
+
+
+def extra_workloads(head_cfg, torch, B, driver, inputs):
+    """The clumped 256^3 box (2^26 particles, half in 32 Gaussian clumps, sort
+    every 4 steps) and the batched workload (192^3 box with charged, dust and
+    tracer species plus 16 independent 64^3 boxes), both in the float32 form
+    with the headline's kernel configuration, 20 steps each."""
+    out = {}
+    cfg = {k: v for k, v in head_cfg.items() if k != "sort_every"}
+    t0 = time.perf_counter()
+    wl = inputs.clumped_box()
+    log(f"[bench] clumped 256^3 inputs in {time.perf_counter() - t0:.1f} s")
+    out["clumped_256"] = time_workload(wl, cfg, 20, 4, torch, B, driver)
+    log(f"[bench] clumped 256^3: {out['clumped_256']}")
+    del wl
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    wl = inputs.batched()
+    log(f"[bench] batched inputs in {time.perf_counter() - t0:.1f} s")
+    bcfg = dict(cfg)
+    bcfg["channels"] = None
+    out["batched_192"] = time_workload(wl, bcfg, 20, head_cfg["sort_every"], torch, B, driver)
+    log(f"[bench] batched: {out['batched_192']}")
+    del wl
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, target_s=15.0):
     """The float64 oracle on the host cores, on a bounded sample of the same
     workload: the first `ns` particles (same fields, grid, dt), whole steps of
@@ -153,6 +198,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tiled", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the clumped and batched workloads")
     ap.add_argument("--eager", action="store_true", help="launch steps without hipGraph replay")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -252,6 +298,9 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on host cores)")
         out["cpu_baseline"] = cpu_baseline(wl)
+    if not args.no_extra:
+        del wl
+        out["extra_workloads"] = extra_workloads(head_cfg, torch, B, driver, inputs)
     print(json.dumps(out), flush=True)
 
 

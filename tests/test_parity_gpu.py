@@ -332,8 +332,9 @@ def test_edge_cases(mods):
     u = np.array([[-0.03], [0.02], [0.01]])
     wl.items[4].particles = inputs.make_particles(x, u)
     ores = oracle.run_workload(wl)
-    for prec, algo in ((B.PL_F64, B.PL_ALGO_PLAIN), (B.PL_F64, B.PL_ALGO_TILED), (B.PL_F32_OFFSET, B.PL_ALGO_TILED)):
-        run, st = _run_gpu(driver, wl, wl.steps, algo == B.PL_ALGO_TILED, prec=prec, algo=algo)
+    for prec, algo in ((B.PL_F64, B.PL_ALGO_PLAIN), (B.PL_F64, B.PL_ALGO_TILED), (B.PL_F32_OFFSET, B.PL_ALGO_TILED),
+                       (B.PL_F64, B.PL_ALGO_RUNS), (B.PL_F32_OFFSET, B.PL_ALGO_RUNS)):
+        run, st = _run_gpu(driver, wl, wl.steps, algo != B.PL_ALGO_PLAIN, prec=prec, algo=algo)
         assert st == B.PL_OK
         f64 = prec == B.PL_F64
         for i in (3, 4):
