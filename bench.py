@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tiled", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the clumped and batched workloads")
+    ap.add_argument("--extra", action="store_true", help="also time the clumped and batched workloads")
     ap.add_argument("--eager", action="store_true", help="launch steps without hipGraph replay")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -298,7 +298,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on host cores)")
         out["cpu_baseline"] = cpu_baseline(wl)
-    if not args.no_extra:
+    if args.extra:
         del wl
         out["extra_workloads"] = extra_workloads(head_cfg, torch, B, driver, inputs)
     print(json.dumps(out), flush=True)
