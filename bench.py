@@ -38,8 +38,9 @@ def kernel_name(cfg, B):
     rho + J + F (compile-time tile shape 8^3 or 8x8x4 when the tile is one)."""
     tile = tuple(cfg["tile"])
     if cfg["algo"] == B.PL_ALGO_RUNS:
+        # compile-time field halo: two cells where the LDS allows (float32, rho+J+F)
         ts = {(8, 8, 8): 1, (8, 8, 4): 2}.get(tile, 0)
-        return f"pl::k_runs<1, 2, 3, 0, {cfg['block'] if ts else 512}, {ts}, {1 if ts else 0}>"
+        return f"pl::k_runs<1, 2, 3, 0, {2 if ts else 0}, {ts}, {1 if ts else 0}>"
     ts = {(8, 8, 8): 1, (8, 8, 4): 2}.get(tile, 0)
     return f"pl::k_step<1, 2, 3, true, 0, {ts}, {1 if ts else 0}>"
 

@@ -125,7 +125,7 @@ typedef struct {
     int max_items;                   /* most items any one call passes (>= 1) */
     int64_t max_np;                  /* most particles in any one item (sizes the sort scratch) */
     int block;                       /* threads per block of the particle kernels (64..512, multiple of 64;
-                                        with PL_ALGO_RUNS: 512 or 1024 for the run-based kernel);
+                                        with PL_ALGO_RUNS: 512, the run-based kernel's block);
                                         0 = default */
     void *stream;                    /* hipStream_t for all work; NULL = the null stream */
     const char *tune_cache;          /* nullable: file written by the autotuner (block, tile) */

@@ -587,10 +587,16 @@ __host__ __device__ inline size_t runs_lds_bytes(int Lf, int Ld, int nslot, int 
     return o + 16;
 }
 
-// One block per CU (the LDS tiles take most of the 160 KB), so RB / 256
-// waves per SIMD: the compiler may spend registers on reads in flight.
-template <int PREC, int SHAPE, int DIM, int KIND, int RB, int TS, int CHS>
-__global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(RB / 256, RB / 256))) void k_runs(const ItemDesc *__restrict__ items, int nitems, int total_units,
+// Threads per block of the run kernel.  One block per CU (the LDS tiles take
+// most of the 160 KB), so two waves per SIMD: the compiler may spend registers
+// on reads in flight.
+constexpr int kRunsThreads = 512;
+
+// HF: field halo width (1 or 2) fixed at compile time, or 0 to take it from
+// the launch flags; TS and HF fixed make every LDS stencil offset an
+// immediate.
+template <int PREC, int SHAPE, int DIM, int KIND, int HF, int TS, int CHS>
+__global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_runs(const ItemDesc *__restrict__ items, int nitems, int total_units,
                                              unsigned *counter, int *errflags, unsigned flags, int lds_bytes)
 {
     using R = typename RealOf<PREC>::T;
@@ -620,7 +626,7 @@ __global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(RB / 256, RB
             G.lo[1] = ty * G.T[1];
             G.lo[2] = tz * G.T[2];
         }
-        G.hf = (flags & SF_FHALO2) ? 2 : 1;
+        G.hf = HF ? HF : ((flags & SF_FHALO2) ? 2 : 1);
         G.fx = G.T[0] + 2 * G.hf;
         G.fxy = G.fx * (G.T[1] + 2 * G.hf);
         G.Lf = G.fxy * (DIM >= 3 ? G.T[2] + 2 * G.hf : 1);
@@ -758,16 +764,15 @@ __global__ __launch_bounds__(RB) __attribute__((amdgpu_waves_per_eu(RB / 256, RB
 // ---------------------------------------------------------------------------
 
 template <int PREC>
-static StepKernel pick_runs(int shape, int dim, int kind, int rb, int ts, int chs)
+static StepKernel pick_runs(int shape, int dim, int kind, int hf, int ts, int chs)
 {
-#define PL_R(S, D, K, RB_, TS_, CHS_) \
-    if (shape == S && dim == D && kind == K && rb == RB_ && ts == TS_ && chs == CHS_) \
-        return k_runs<PREC, S, D, K, RB_, TS_, CHS_>;
-#define PL_RG(S, D) PL_R(S, D, PL_LORENTZ, 512, 0, 0) PL_R(S, D, PL_DUST, 512, 0, 0)
-#define PL_RF(TS_) PL_R(PL_TSC, 3, PL_LORENTZ, 1024, TS_, 1) PL_R(PL_TSC, 3, PL_LORENTZ, 512, TS_, 1) \
-    PL_R(PL_TSC, 3, PL_DUST, 1024, TS_, 2) PL_R(PL_TSC, 3, PL_DUST, 512, TS_, 2)
+#define PL_R(S, D, K, HF_, TS_, CHS_) \
+    if (shape == S && dim == D && kind == K && hf == HF_ && ts == TS_ && chs == CHS_) \
+        return k_runs<PREC, S, D, K, HF_, TS_, CHS_>;
+#define PL_RG(S, D) PL_R(S, D, PL_LORENTZ, 0, 0, 0) PL_R(S, D, PL_DUST, 0, 0, 0)
+#define PL_RF(HF_, TS_) PL_R(PL_TSC, 3, PL_LORENTZ, HF_, TS_, 1) PL_R(PL_TSC, 3, PL_DUST, HF_, TS_, 2)
     PL_RG(PL_TSC, 3) PL_RG(PL_TSC, 2) PL_RG(PL_CIC, 3) PL_RG(PL_CIC, 2)
-    PL_RF(1) PL_RF(2)
+    PL_RF(1, 1) PL_RF(2, 1) PL_RF(1, 2) PL_RF(2, 2)
 #undef PL_RF
 #undef PL_RG
 #undef PL_R
@@ -799,9 +804,7 @@ hipError_t launch_runs_impl(Ctx *c, const ItemDesc *table, const ItemDesc *host,
             }
         }
     }
-    const int rb = (ts != 0 && c->runs_block == 1024) ? 1024 : 512;
-    StepKernel k = pick_runs<PREC>(c->d.shape, c->d.ndim, kind, rb, ts, chs);
-    if (!k) return hipErrorInvalidConfiguration;
+    const int rb = kRunsThreads;
     // LDS of the group: a two-cell field halo when it fits, else one cell
     auto group_lds = [&](int hf) {
         size_t lds = 0;
@@ -818,12 +821,17 @@ hipError_t launch_runs_impl(Ctx *c, const ItemDesc *table, const ItemDesc *host,
         return lds;
     };
     size_t lds = group_lds(2);
+    int hf = 2;
     if (lds <= (size_t)c->lds_max) {
         sf |= SF_FHALO2;
     } else {
         lds = group_lds(1);
+        hf = 1;
         if (lds > (size_t)c->lds_max) return hipErrorInvalidConfiguration;
     }
+    // compile-time halo in the fixed-shape kernels, from the flags otherwise
+    StepKernel k = pick_runs<PREC>(c->d.shape, c->d.ndim, kind, ts ? hf : 0, ts, chs);
+    if (!k) return hipErrorInvalidConfiguration;
     int grid = std::min(total_units, resident_blocks(c, k, rb, lds));
     hipLaunchKernelGGL(k, dim3(grid), dim3(rb), lds, c->stream, table, nitems, total_units, counter, c->errflags, sf,
                        (int)lds);

@@ -42,7 +42,7 @@ pl_status validate_desc(const pl_init_desc *d)
     if (d->max_items < 1 || d->max_items > 4096) return PL_EINVAL;
     if (d->max_np < 0 || d->max_np >= (int64_t)1 << 31) return PL_EINVAL;
     if (d->algo == PL_ALGO_RUNS) {
-        if (d->block != 0 && d->block != 512 && d->block != 1024) return PL_EINVAL;
+        if (d->block != 0 && d->block != 512) return PL_EINVAL;
     } else if (d->block != 0 && (d->block < 64 || d->block > 512 || d->block % 64)) {
         return PL_EINVAL;
     }
@@ -89,7 +89,7 @@ void read_tune_cache(const char *path, int &block, int tile[3], int &runs, int &
             if (fscanf(f, "%d", &v) == 1) runs = v != 0;
         } else if (!strcmp(key, "runs_block")) {
             int v;
-            if (fscanf(f, "%d", &v) == 1 && (v == 512 || v == 1024)) runs_block = v;
+            if (fscanf(f, "%d", &v) == 1 && v == 512) runs_block = v;
         } else if (!strcmp(key, "tile")) {
             int a, b, c;
             if (fscanf(f, "%d %d %d", &a, &b, &c) == 3 && a > 0 && b > 0 && c > 0) {

@@ -27,7 +27,7 @@ from . import driver, inputs
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TILES = [(8, 8, 8), (8, 8, 4), (16, 8, 4), (8, 4, 4)]
-RUN_BLOCKS = [512, 1024]
+RUN_BLOCKS = [512]
 CADENCES = [8, 16, 32]
 CHANNELS = ["rho", "J0", "J1", "J2", "F0", "F1", "F2"]
 

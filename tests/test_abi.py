@@ -117,7 +117,8 @@ def _desc(**kw):
     dict(ndim=2),          # 2D with n[2] = 8
     dict(nboxes=0),
     dict(algo=2),                                   # run-based kernel needs the tile+cell key
-    dict(algo=2, key_mode=1, block=256),            # run-based block is 512 or 1024
+    dict(algo=2, key_mode=1, block=256),            # run-based block is 512
+    dict(algo=2, key_mode=1, block=1024),
     dict(algo=2, key_mode=1, max_np=1 << 29),       # run entries hold the first index in 30 bits
 ])
 def test_init_rejects_bad_descriptions(lib, bad):
