@@ -148,9 +148,10 @@ typedef struct {
     void *fp[3];            /* nullable: per-particle force m w du/dt, written by gather_push, read by deposit */
     int32_t *tile_start;    /* ntiles+1 first-particle offsets per tile, written by pl_part_sort;
                                required by PL_ALGO_TILED and PL_ALGO_RUNS */
-    int32_t *runs;          /* nullable: n + ntiles run-table entries written by pl_part_sort
+    int32_t *runs;          /* nullable: n + 2*ntiles run-table entries written by pl_part_sort
                                with PL_ALGO_RUNS (runs of tile t at [tile_start[t], ...), their
-                               count at runs[n + t]); required by PL_ALGO_RUNS, n < 2^29 */
+                               count at runs[n + t], the tiles in processing order at
+                               runs[n + ntiles + g]); required by PL_ALGO_RUNS, n < 2^29 */
 } pl_particles;
 
 typedef struct {
@@ -214,7 +215,9 @@ pl_status pl_part_deposit(pl_ctx *ctx, const pl_item *items, int nitems, uint32_
  * With PL_ALGO_RUNS it also writes p.runs: the particles of every cell are
  * cut into runs of up to four consecutive sorted particles, and the runs of a
  * tile are listed by (index of the run inside its cell, cell in tile), each
- * entry holding (first particle << 2) | (length - 1).
+ * entry holding (first particle << 2) | (length - 1); the tiles are listed in
+ * processing order: those with more than twice the mean run count first, by
+ * decreasing count, then the others in index order.
  */
 pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems);
 

@@ -613,7 +613,9 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
         if (g < 0) break;
         const int iti = find_item(items, nitems, g);
         const ItemDesc &I = items[iti];
-        const int t = g - I.unit_begin;
+        // the sort lists the tiles longest first
+        const int t = I.runs[I.np + I.ntiles + (g - I.unit_begin)];
+        if ((unsigned)t >= (unsigned)I.ntiles) continue;      // uniform
         RunGeo G;
         G.T[0] = TS ? ts_dim(TS, 0) : I.tile[0];
         G.T[1] = TS ? ts_dim(TS, 1) : I.tile[1];
@@ -685,16 +687,22 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
         }
 
         // this thread's runs r = tid, tid + blockDim, ..., each cut into
-        // batches of KR; the next batch is fetched before the current one runs
+        // batches of KR; the next batch is fetched before the current one runs.
+        // A crowded tile is taken in segments of 2 * blockDim runs with the
+        // LDS queues drained between segments when half full; every tile ends
+        // with a drain.  Segment count, drain decisions and barriers are
+        // uniform across the block.
         const gptr<const int32_t> runs = (gptr<const int32_t>)(I.runs + pbeg);
         auto run_span = [&](int r, int &rs, int &rl) {
             const int e = runs[r];
             rs = min(max(e >> 2, pbeg), pend - 1);
             rl = min((e & 3) + 1, pend - rs);
         };
-        {
-            int r = threadIdx.x, b = 0, rs = 0, rl = 0;
-            bool have = r < nruns;
+        const int seg = 2 * (int)blockDim.x;
+        for (int s0 = 0; s0 < nruns; s0 += seg) {
+            const int s1 = min(nruns, s0 + seg);
+            int r = s0 + (int)threadIdx.x, b = 0, rs = 0, rl = 0;
+            bool have = r < s1;
             BatchRaw<PREC, DIM, KR> cur;
             if (have) {
                 run_span(r, rs, rl);
@@ -705,9 +713,9 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
                 if (nb >= rl) {
                     nr = r + blockDim.x;
                     nb = 0;
-                    if (nr < nruns) run_span(nr, nrs, nrl);
+                    if (nr < s1) run_span(nr, nrs, nrl);
                 }
-                const bool nhave = nr < nruns;
+                const bool nhave = nr < s1;
                 BatchRaw<PREC, DIM, KR> nxt;
                 if (nhave) fetch_batch<PREC, DIM, KR>(U, nrs + nb, min(KR, nrl - nb), nxt);
                 run_batch<PREC, SHAPE, DIM, KIND, CHS, KR>(U, G, S, cur, do_sums, err);
@@ -718,13 +726,23 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
                 rl = nrl;
                 have = nhave;
             }
+            __syncthreads();
+            const int qg = ctl[1], qd = ctl[2];
+            __syncthreads();          // all threads hold the same counts before anyone queues again
+            if (s1 >= nruns || 2 * qg > gq_cap(G.hf) || 2 * qd > RunsQ<PREC>::DQ) {
+                const int ng = min(qg, gq_cap(G.hf));
+                for (int i = threadIdx.x; i < ng; i += blockDim.x)
+                    particle_single<PREC, SHAPE, DIM, KIND, CHS>(U, G, S, S.gq[i], do_sums, err);
+                const int nd = min(qd, RunsQ<PREC>::DQ);
+                for (int i = threadIdx.x; i < nd; i += blockDim.x) record_deposit<PREC, SHAPE, DIM, CHS>(U, G, S, i);
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    ctl[1] = 0;
+                    ctl[2] = 0;
+                }
+                __syncthreads();
+            }
         }
-        __syncthreads();
-        const int ng = min(ctl[1], gq_cap(G.hf));
-        for (int i = threadIdx.x; i < ng; i += blockDim.x)
-            particle_single<PREC, SHAPE, DIM, KIND, CHS>(U, G, S, S.gq[i], do_sums, err);
-        const int nd = min(ctl[2], RunsQ<PREC>::DQ);
-        for (int i = threadIdx.x; i < nd; i += blockDim.x) record_deposit<PREC, SHAPE, DIM, CHS>(U, G, S, i);
 
         // flush the deposit tile: one float64 global atomic per touched cell and channel
         __syncthreads();

@@ -300,6 +300,68 @@ __global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t
     }
 }
 
+// Work-unit order of the run-based kernel (one block): tiles holding more
+// than twice the mean number of runs first, by decreasing run count (ties by
+// tile index), then every other tile in index order.  Longest-first claiming
+// keeps one crowded tile from finishing last on its CU.  The first kHeavyMax
+// such tiles (in index order) are ranked; later ones keep index order.
+// Written to runs[np + ntiles + g] for unit g.  Every loop that contains a
+// block scan has the same trip count in all threads.
+constexpr int kOrderThreads = 1024;
+constexpr int kHeavyMax = 1024;
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(int32_t *runs, int np, int ntiles)
+{
+    __shared__ uint32_t sh[kOrderThreads / 64 + 1];
+    __shared__ int hv_tile[kHeavyMax];
+    __shared__ int hv_cnt[kHeavyMax];
+    __shared__ unsigned long long s_total;
+    const int32_t *cnt = runs + np;
+    int32_t *order = runs + np + ntiles;
+    if (threadIdx.x == 0) s_total = 0ull;
+    __syncthreads();
+    unsigned long long mine = 0;
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) mine += (unsigned long long)max(cnt[t], 0);
+    atomicAdd(&s_total, mine);
+    __syncthreads();
+    const long long thr = 2 * (long long)(s_total / (unsigned long long)max(ntiles, 1)) + 1;
+    // ranked heavy tiles: the first kHeavyMax heavy tiles in index order
+    uint32_t hbase = 0;
+    for (int t0 = 0; t0 < ntiles; t0 += blockDim.x) {
+        const int t = t0 + threadIdx.x;
+        const bool h = t < ntiles && (long long)cnt[t] > thr;
+        uint32_t tot;
+        const uint32_t hp = hbase + block_exclusive_scan(h ? 1u : 0u, sh, tot);
+        if (h && hp < (uint32_t)kHeavyMax) {
+            hv_tile[hp] = t;
+            hv_cnt[hp] = cnt[t];
+        }
+        hbase += tot;
+    }
+    const int nh = (int)min(hbase, (uint32_t)kHeavyMax);
+    __syncthreads();
+    // every other tile in index order after the ranked ones
+    uint32_t hb = 0, lb = 0;
+    for (int t0 = 0; t0 < ntiles; t0 += blockDim.x) {
+        const int t = t0 + threadIdx.x;
+        const bool h = t < ntiles && (long long)cnt[t] > thr;
+        uint32_t toth, totl;
+        const uint32_t hp = hb + block_exclusive_scan(h ? 1u : 0u, sh, toth);
+        const bool ranked = h && hp < (uint32_t)kHeavyMax;
+        const bool light = t < ntiles && !ranked;
+        const uint32_t lp = lb + block_exclusive_scan(light ? 1u : 0u, sh, totl);
+        if (light) order[nh + (int)lp] = t;
+        hb += toth;
+        lb += totl;
+    }
+    // ranked tiles by decreasing run count, ties by tile index
+    for (int i = threadIdx.x; i < nh; i += blockDim.x) {
+        int rank = 0;
+        for (int j = 0; j < nh; ++j)
+            rank += hv_cnt[j] > hv_cnt[i] || (hv_cnt[j] == hv_cnt[i] && hv_tile[j] < hv_tile[i]);
+        order[rank] = hv_tile[i];
+    }
+}
+
 __global__ void k_fill_i32(int32_t *p, int n, int v)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
@@ -348,7 +410,8 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
         if (a.runs) {
             hipLaunchKernelGGL(k_fill_i32, dim3(std::max(1, (a.ntiles + 256) / 256)), dim3(256), 0, s, a.runs,
                                a.ntiles, 0);
-            c->stats[0]++;
+            hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, a.runs, 0, a.ntiles);
+            c->stats[0] += 2;
         }
         return hipGetLastError();
     }
@@ -390,7 +453,8 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
         // keys are tile * cells_per_tile + cell in tile (PL_KEY_TILE_CELL)
         hipLaunchKernelGGL(k_runs_build, dim3(std::min(a.ntiles, 8 * c->num_cu)), dim3(kRunsBuildThreads), 0, s,
                            c->keys[src], a.np, per_tile_cells, a.ntiles, a.tile_start, a.runs);
-        c->stats[0]++;
+        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, a.runs, a.np, a.ntiles);
+        c->stats[0] += 2;
     }
     return hipGetLastError();
 }

@@ -75,13 +75,30 @@ def expected_runs(sorted_keys, per_tile, ntiles):
     return out, tstart
 
 
+def expected_order(counts):
+    """Tiles with more than twice the mean run count first (by decreasing
+    count, ties by index; at most 1024 of them, the first in index order),
+    then the others in index order."""
+    ntiles = len(counts)
+    thr = 2 * (int(counts.sum()) // max(ntiles, 1)) + 1
+    heavy = [t for t in range(ntiles) if counts[t] > thr][:1024]
+    hs = set(heavy)
+    ranked = sorted(heavy, key=lambda t: (-counts[t], t))
+    return np.array(ranked + [t for t in range(ntiles) if t not in hs], dtype=np.int64)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_runs_table_exact(mods, prec):
     oracle, driver, inputs, B = mods
     for n, npart, tile in ((32, 8 * 32 ** 3 - 37, (8, 8, 8)), (16, 1, (4, 4, 4)), (16, 3001, (16, 8, 2)),
-                           (16, 20000, (4, 4, 4))):
+                           (16, 20000, (4, 4, 4)), (32, -1, (4, 4, 4))):
         say(f"[runs] run table {prec} n={n} np={npart} tile={tile}")
-        wl = inputs.turbulent_box(n=n, npart=npart, steps=0)
+        if npart < 0:
+            # clumped: crowded tiles that go first in the order
+            wl = inputs.clumped_box(n=n, npart=60000, nclumps=3, sigma=1.5, steps=0)
+            npart = wl.items[0].particles.n
+        else:
+            wl = inputs.turbulent_box(n=n, npart=npart, steps=0)
         p = B.PL_F64 if prec == "f64" else B.PL_F32_OFFSET
         run = driver.Run(wl, prec=p, algo=B.PL_ALGO_RUNS, tile=tile)
         run.sort()
@@ -100,12 +117,13 @@ def test_runs_table_exact(mods, prec):
         per_tile = tile[0] * tile[1] * tile[2]
         exp, tstart = expected_runs(keys[perm], per_tile, ntiles)
         assert np.array_equal(raw["tile_start"][: ntiles + 1], tstart)
-        got = raw["runs"][: npart + ntiles].astype(np.int64)
+        got = raw["runs"][: npart + 2 * ntiles].astype(np.int64)
         for t in range(ntiles):
             beg = tstart[t]
             nr = exp[npart + t]
             assert got[npart + t] == nr, (t, got[npart + t], nr)
             assert np.array_equal(got[beg:beg + nr], exp[beg:beg + nr]), t
+        assert np.array_equal(got[npart + ntiles:], expected_order(exp[npart:npart + ntiles]))
         run.close()
 
 
