@@ -83,6 +83,11 @@ typedef int pl_status;
                               tracers and deposit-only calls run the PL_ALGO_TILED kernel).
                               Needs pl_part_sort with PL_KEY_TILE_CELL, which writes p.runs */
 
+/* Work units beyond one per tile that pl_part_sort may create by splitting
+ * crowded tiles (PL_ALGO_RUNS), and the length of the run table. */
+#define PL_RUNS_SPLIT_UNITS 1024
+#define PL_RUNS_LEN(n, ntiles) ((int64_t)(n) + 3 * (int64_t)(ntiles) + 2 * PL_RUNS_SPLIT_UNITS + 1)
+
 #define PL_KEY_TILE       0  /* sort by tile */
 #define PL_KEY_TILE_CELL  1  /* sort by tile, then by cell inside the tile (x fastest) */
 #define PL_KEY_TILE_RANK  2  /* sort by tile, then by rank among the particles of the same cell
@@ -148,10 +153,13 @@ typedef struct {
     void *fp[3];            /* nullable: per-particle force m w du/dt, written by gather_push, read by deposit */
     int32_t *tile_start;    /* ntiles+1 first-particle offsets per tile, written by pl_part_sort;
                                required by PL_ALGO_TILED and PL_ALGO_RUNS */
-    int32_t *runs;          /* nullable: n + 2*ntiles run-table entries written by pl_part_sort
-                               with PL_ALGO_RUNS (runs of tile t at [tile_start[t], ...), their
-                               count at runs[n + t], the tiles in processing order at
-                               runs[n + ntiles + g]); required by PL_ALGO_RUNS, n < 2^29 */
+    int32_t *runs;          /* nullable: PL_RUNS_LEN(n, ntiles) run-table entries written by
+                               pl_part_sort with PL_ALGO_RUNS: the runs of tile t at
+                               [tile_start[t], ...), their count at runs[n + t], the work units
+                               in processing order as pairs (tile, piece | npieces << 16) at
+                               runs[n + ntiles + 2g], and the number of units at
+                               runs[n + ntiles + 2 * (ntiles + PL_RUNS_SPLIT_UNITS)]; required by
+                               PL_ALGO_RUNS, n < 2^29 */
 } pl_particles;
 
 typedef struct {
@@ -215,9 +223,14 @@ pl_status pl_part_deposit(pl_ctx *ctx, const pl_item *items, int nitems, uint32_
  * With PL_ALGO_RUNS it also writes p.runs: the particles of every cell are
  * cut into runs of up to four consecutive sorted particles, and the runs of a
  * tile are listed by (index of the run inside its cell, cell in tile), each
- * entry holding (first particle << 2) | (length - 1); the tiles are listed in
- * processing order: those with more than twice the mean run count first, by
- * decreasing count, then the others in index order.
+ * entry holding (first particle << 2) | (length - 1).  It then lists the
+ * work units of the run kernel: with P = max(ceil(total runs / 1024), 1024)
+ * runs, a tile of c runs becomes ceil(c / P) pieces of equal run count (an
+ * empty tile none).  Tiles cut into several pieces or holding more than twice
+ * the mean run count come first (the first 1024 such tiles in index order,
+ * by decreasing runs per piece, ties by tile index), each with its pieces in
+ * order, then the other non-empty tiles in index order.  Piece k of a tile
+ * takes runs [c*k/npieces, c*(k+1)/npieces).
  */
 pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems);
 

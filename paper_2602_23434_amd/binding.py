@@ -19,6 +19,12 @@ PL_CIC, PL_TSC = 1, 2
 PL_LORENTZ, PL_DUST, PL_TRACER = 0, 1, 2
 PL_ALGO_PLAIN, PL_ALGO_TILED, PL_ALGO_RUNS = 0, 1, 2
 PL_KEY_TILE, PL_KEY_TILE_CELL, PL_KEY_TILE_RANK = 0, 1, 2
+PL_RUNS_SPLIT_UNITS = 1024
+
+
+def runs_len(n, ntiles):
+    """PL_RUNS_LEN: entries of the run table of n particles over ntiles tiles."""
+    return n + 3 * ntiles + 2 * PL_RUNS_SPLIT_UNITS + 1
 PL_FUSE_DEPOSIT, PL_ZERO_FIRST, PL_GRAPH, PL_SUMS = 1, 2, 4, 8
 
 EXPORTS = ["pl_part_init", "pl_part_gather_push", "pl_part_deposit", "pl_part_sort", "pl_part_pack",

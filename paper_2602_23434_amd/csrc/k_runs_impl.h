@@ -611,11 +611,24 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
     for (;;) {
         int g = claim_unit(counter, total_units, ctl);
         if (g < 0) break;
-        const int iti = find_item(items, nitems, g);
+        // item k of the launch owns units [unit_begin + k * kRunsSplit, + nunits + kRunsSplit)
+        int iti = 0;
+        while (iti + 1 < nitems && items[iti + 1].unit_begin + (iti + 1) * kRunsSplit <= g) ++iti;
         const ItemDesc &I = items[iti];
-        // the sort lists the tiles longest first
-        const int t = I.runs[I.np + I.ntiles + (g - I.unit_begin)];
-        if ((unsigned)t >= (unsigned)I.ntiles) continue;      // uniform
+        const int ubeg = I.unit_begin + iti * kRunsSplit;
+        const int ucap = I.nunits + kRunsSplit;
+        const int local = g - ubeg;
+        const int nu = min(max(I.runs[runs_count_at(I.np, I.ntiles)], 0), I.nunits > 0 ? ucap : 0);
+        if (local >= nu) {
+            // the rest of this item's units are empty: move the counter past them
+            if (threadIdx.x == 0) atomicMax(counter, (unsigned)(ubeg + ucap));
+            continue;                                          // uniform
+        }
+        // the sort lists the units largest first: (tile, piece | npieces << 16)
+        const int32_t *unit = I.runs + runs_units_at(I.np, I.ntiles) + 2 * local;
+        const int t = unit[0];
+        const int piece = unit[1] & 0xffff, npieces = unit[1] >> 16;
+        if ((unsigned)t >= (unsigned)I.ntiles || npieces < 1 || piece >= npieces) continue;      // uniform
         RunGeo G;
         G.T[0] = TS ? ts_dim(TS, 0) : I.tile[0];
         G.T[1] = TS ? ts_dim(TS, 1) : I.tile[1];
@@ -638,7 +651,9 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
         const int pbeg = min(max(I.tile_start[t], 0), I.np);
         const int pend = min(max(I.tile_start[t + 1], pbeg), I.np);
         const int nruns = min(max(I.runs[I.np + t], 0), pend - pbeg);
-        if (nruns == 0) continue;          // uniform: the whole block skips an empty tile
+        const int r_lo = (int)((long long)nruns * piece / npieces);
+        const int r_hi = (int)((long long)nruns * (piece + 1) / npieces);
+        if (r_hi <= r_lo) continue;        // uniform: the whole block skips an empty piece
 
         UnitC<PREC> U;
         load_unit<PREC>(I, U, G.Ld);
@@ -686,21 +701,22 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
             __syncthreads();
         }
 
-        // this thread's runs r = tid, tid + blockDim, ..., each cut into
+        // this thread's runs r = r_lo + tid, + blockDim, ..., each cut into
         // batches of KR; the next batch is fetched before the current one runs.
-        // A crowded tile is taken in segments of 2 * blockDim runs with the
-        // LDS queues drained between segments when half full; every tile ends
+        // A long piece is taken in segments of 4 * blockDim runs with the LDS
+        // queues drained between segments when half full; every piece ends
         // with a drain.  Segment count, drain decisions and barriers are
-        // uniform across the block.
+        // uniform across the block.  Pieces of one tile on several CUs meet
+        // only in the global atomics of the flush.
         const gptr<const int32_t> runs = (gptr<const int32_t>)(I.runs + pbeg);
         auto run_span = [&](int r, int &rs, int &rl) {
             const int e = runs[r];
             rs = min(max(e >> 2, pbeg), pend - 1);
             rl = min((e & 3) + 1, pend - rs);
         };
-        const int seg = 2 * (int)blockDim.x;
-        for (int s0 = 0; s0 < nruns; s0 += seg) {
-            const int s1 = min(nruns, s0 + seg);
+        const int seg = 4 * (int)blockDim.x;
+        for (int s0 = r_lo; s0 < r_hi; s0 += seg) {
+            const int s1 = min(r_hi, s0 + seg);
             int r = s0 + (int)threadIdx.x, b = 0, rs = 0, rl = 0;
             bool have = r < s1;
             BatchRaw<PREC, DIM, KR> cur;
@@ -729,7 +745,7 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
             __syncthreads();
             const int qg = ctl[1], qd = ctl[2];
             __syncthreads();          // all threads hold the same counts before anyone queues again
-            if (s1 >= nruns || 2 * qg > gq_cap(G.hf) || 2 * qd > RunsQ<PREC>::DQ) {
+            if (s1 >= r_hi || 2 * qg > gq_cap(G.hf) || 2 * qd > RunsQ<PREC>::DQ) {
                 const int ng = min(qg, gq_cap(G.hf));
                 for (int i = threadIdx.x; i < ng; i += blockDim.x)
                     particle_single<PREC, SHAPE, DIM, KIND, CHS>(U, G, S, S.gq[i], do_sums, err);
@@ -850,8 +866,10 @@ hipError_t launch_runs_impl(Ctx *c, const ItemDesc *table, const ItemDesc *host,
     // compile-time halo in the fixed-shape kernels, from the flags otherwise
     StepKernel k = pick_runs<PREC>(c->d.shape, c->d.ndim, kind, ts ? hf : 0, ts, chs);
     if (!k) return hipErrorInvalidConfiguration;
-    int grid = std::min(total_units, resident_blocks(c, k, rb, lds));
-    hipLaunchKernelGGL(k, dim3(grid), dim3(rb), lds, c->stream, table, nitems, total_units, counter, c->errflags, sf,
+    // every item has kRunsSplit units beyond its tiles for the pieces of crowded tiles
+    const int units = total_units + nitems * kRunsSplit;
+    int grid = std::min(units, resident_blocks(c, k, rb, lds));
+    hipLaunchKernelGGL(k, dim3(grid), dim3(rb), lds, c->stream, table, nitems, units, counter, c->errflags, sf,
                        (int)lds);
     c->stats[0]++;
     c->stats[4]++;

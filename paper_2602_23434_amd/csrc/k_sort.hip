@@ -300,66 +300,102 @@ __global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t
     }
 }
 
-// Work-unit order of the run-based kernel (one block): tiles holding more
-// than twice the mean number of runs first, by decreasing run count (ties by
-// tile index), then every other tile in index order.  Longest-first claiming
-// keeps one crowded tile from finishing last on its CU.  The first kHeavyMax
-// such tiles (in index order) are ranked; later ones keep index order.
-// Written to runs[np + ntiles + g] for unit g.  Every loop that contains a
-// block scan has the same trip count in all threads.
+// Work units of the run-based kernel (one block).  With P = max(ceil(total
+// runs / kRunsSplit), kRunsMinPiece), a tile of c runs becomes ceil(c / P)
+// pieces (an empty tile none), so at most ntiles + kRunsSplit units exist.
+// Tiles cut into pieces or holding more than twice the mean run count go
+// first, by decreasing runs per piece (ties by tile index), each followed by
+// its pieces in order; then every other non-empty tile in index order.  The
+// first kRankMax such tiles (in index order) are ranked; later ones keep index
+// order.  Largest-first claiming keeps a crowded tile from finishing last on
+// its CU, and splitting keeps one tile from outweighing a CU's share of the
+// step.  Every loop that contains a block scan has the same trip count in all
+// threads.
 constexpr int kOrderThreads = 1024;
-constexpr int kHeavyMax = 1024;
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(int32_t *runs, int np, int ntiles)
+constexpr int kRankMax = 1024;
+__global__ __launch_bounds__(kOrderThreads) void k_unit_list(int32_t *runs, int np, int ntiles)
 {
     __shared__ uint32_t sh[kOrderThreads / 64 + 1];
-    __shared__ int hv_tile[kHeavyMax];
-    __shared__ int hv_cnt[kHeavyMax];
+    __shared__ int rk_tile[kRankMax];
+    __shared__ int rk_cnt[kRankMax];
+    __shared__ int rk_k[kRankMax];
+    __shared__ int by_rank[kRankMax];
     __shared__ unsigned long long s_total;
     const int32_t *cnt = runs + np;
-    int32_t *order = runs + np + ntiles;
+    int32_t *units = runs + runs_units_at(np, ntiles);
+    const long long cap = (long long)ntiles + kRunsSplit;
     if (threadIdx.x == 0) s_total = 0ull;
     __syncthreads();
     unsigned long long mine = 0;
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x) mine += (unsigned long long)max(cnt[t], 0);
     atomicAdd(&s_total, mine);
     __syncthreads();
-    const long long thr = 2 * (long long)(s_total / (unsigned long long)max(ntiles, 1)) + 1;
-    // ranked heavy tiles: the first kHeavyMax heavy tiles in index order
+    const long long total = (long long)s_total;
+    const long long pz = max((total + kRunsSplit - 1) / kRunsSplit, (long long)kRunsMinPiece);
+    const long long thr = 2 * (total / max(ntiles, 1)) + 1;
+    auto pieces = [&](int t) -> int {
+        const long long c = max(cnt[t], 0);
+        return (int)((c + pz - 1) / pz);
+    };
+    auto emit = [&](long long at, int t, int k) {
+        for (int p = 0; p < k; ++p)
+            if (at + p < cap) {
+                units[2 * (at + p)] = t;
+                units[2 * (at + p) + 1] = p | (k << 16);
+            }
+    };
+    // ranked tiles: the first kRankMax split or heavy tiles in index order
     uint32_t hbase = 0;
     for (int t0 = 0; t0 < ntiles; t0 += blockDim.x) {
         const int t = t0 + threadIdx.x;
-        const bool h = t < ntiles && (long long)cnt[t] > thr;
+        const int k = t < ntiles ? pieces(t) : 0;
+        const bool h = t < ntiles && (k >= 2 || (long long)cnt[t] > thr);
         uint32_t tot;
         const uint32_t hp = hbase + block_exclusive_scan(h ? 1u : 0u, sh, tot);
-        if (h && hp < (uint32_t)kHeavyMax) {
-            hv_tile[hp] = t;
-            hv_cnt[hp] = cnt[t];
+        if (h && hp < (uint32_t)kRankMax) {
+            rk_tile[hp] = t;
+            rk_cnt[hp] = cnt[t];
+            rk_k[hp] = k;
         }
         hbase += tot;
     }
-    const int nh = (int)min(hbase, (uint32_t)kHeavyMax);
+    const int nh = (int)min(hbase, (uint32_t)kRankMax);
     __syncthreads();
-    // every other tile in index order after the ranked ones
-    uint32_t hb = 0, lb = 0;
+    // rank by decreasing runs per piece (cnt / k, compared exactly), ties by tile
+    for (int i = threadIdx.x; i < nh; i += blockDim.x) {
+        const long long ci = rk_cnt[i], ki = rk_k[i];
+        int rank = 0;
+        for (int j = 0; j < nh; ++j) {
+            const long long a = (long long)rk_cnt[j] * ki, b = ci * (long long)rk_k[j];
+            rank += a > b || (a == b && rk_tile[j] < rk_tile[i]);
+        }
+        by_rank[rank] = i;
+    }
+    __syncthreads();
+    uint32_t nranked;
+    {
+        const int i = threadIdx.x < nh ? by_rank[threadIdx.x] : 0;
+        const uint32_t k = threadIdx.x < nh ? (uint32_t)rk_k[i] : 0u;
+        const uint32_t at = block_exclusive_scan(k, sh, nranked);
+        if (threadIdx.x < nh) emit(at, rk_tile[i], (int)k);
+    }
+    // every other non-empty tile in index order
+    uint32_t hb = 0;
+    long long lb = nranked;
     for (int t0 = 0; t0 < ntiles; t0 += blockDim.x) {
         const int t = t0 + threadIdx.x;
-        const bool h = t < ntiles && (long long)cnt[t] > thr;
+        const int k = t < ntiles ? pieces(t) : 0;
+        const bool h = t < ntiles && (k >= 2 || (long long)cnt[t] > thr);
         uint32_t toth, totl;
         const uint32_t hp = hb + block_exclusive_scan(h ? 1u : 0u, sh, toth);
-        const bool ranked = h && hp < (uint32_t)kHeavyMax;
-        const bool light = t < ntiles && !ranked;
-        const uint32_t lp = lb + block_exclusive_scan(light ? 1u : 0u, sh, totl);
-        if (light) order[nh + (int)lp] = t;
+        const bool ranked = h && hp < (uint32_t)kRankMax;
+        const uint32_t kl = (t < ntiles && !ranked) ? (uint32_t)k : 0u;
+        const uint32_t lp = block_exclusive_scan(kl, sh, totl);
+        if (kl) emit(lb + lp, t, (int)kl);
         hb += toth;
         lb += totl;
     }
-    // ranked tiles by decreasing run count, ties by tile index
-    for (int i = threadIdx.x; i < nh; i += blockDim.x) {
-        int rank = 0;
-        for (int j = 0; j < nh; ++j)
-            rank += hv_cnt[j] > hv_cnt[i] || (hv_cnt[j] == hv_cnt[i] && hv_tile[j] < hv_tile[i]);
-        order[rank] = hv_tile[i];
-    }
+    if (threadIdx.x == 0) runs[runs_count_at(np, ntiles)] = (int32_t)min(lb, cap);
 }
 
 __global__ void k_fill_i32(int32_t *p, int n, int v)
@@ -410,7 +446,7 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
         if (a.runs) {
             hipLaunchKernelGGL(k_fill_i32, dim3(std::max(1, (a.ntiles + 256) / 256)), dim3(256), 0, s, a.runs,
                                a.ntiles, 0);
-            hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, a.runs, 0, a.ntiles);
+            hipLaunchKernelGGL(k_unit_list, dim3(1), dim3(kOrderThreads), 0, s, a.runs, 0, a.ntiles);
             c->stats[0] += 2;
         }
         return hipGetLastError();
@@ -453,7 +489,7 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
         // keys are tile * cells_per_tile + cell in tile (PL_KEY_TILE_CELL)
         hipLaunchKernelGGL(k_runs_build, dim3(std::min(a.ntiles, 8 * c->num_cu)), dim3(kRunsBuildThreads), 0, s,
                            c->keys[src], a.np, per_tile_cells, a.ntiles, a.tile_start, a.runs);
-        hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, a.runs, a.np, a.ntiles);
+        hipLaunchKernelGGL(k_unit_list, dim3(1), dim3(kOrderThreads), 0, s, a.runs, a.np, a.ntiles);
         c->stats[0] += 2;
     }
     return hipGetLastError();

@@ -15,6 +15,16 @@ constexpr int kCellBits = 10;        // packed cell: 10 bits per dimension
 constexpr int kMaxN = 1 << kCellBits;
 constexpr int kRunLen = 4;           // particles per run of the run table (PL_ALGO_RUNS)
 constexpr int kRunsMaxTileCells = 1024;
+constexpr int kRunsSplit = PL_RUNS_SPLIT_UNITS;   // work units beyond one per tile
+constexpr int kRunsMinPiece = 1024;               // smallest run count worth a split
+
+// Run table of an item (PL_ALGO_RUNS), offsets from runs[0]: unit g is the
+// pair at units_at + 2g, the unit count at count_at.
+__host__ __device__ inline int64_t runs_units_at(int64_t np, int ntiles) { return np + ntiles; }
+__host__ __device__ inline int64_t runs_count_at(int64_t np, int ntiles)
+{
+    return np + ntiles + 2 * ((int64_t)ntiles + kRunsSplit);
+}
 
 enum Channel { CH_RHO = 0, CH_J0 = 1, CH_F0 = 4, CH_ENG = 7 };
 

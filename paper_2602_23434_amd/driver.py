@@ -105,8 +105,8 @@ class Run:
                 extra = {
                     "fp": [torch.zeros(n, dtype=fdt, device=self.dev) for _ in range(3)] if fp else None,
                     "tile_start": torch.zeros(bx.n[0] * bx.n[1] * bx.n[2] + 1, dtype=torch.int32, device=self.dev),
-                    # run table: n entries + a count and an order entry per tile (at most one tile per cell)
-                    "runs": (torch.zeros(n + 2 * bx.n[0] * bx.n[1] * bx.n[2] + 1, dtype=torch.int32, device=self.dev)
+                    # run table sized for one tile per cell (the most tiles a box can have)
+                    "runs": (torch.zeros(B.runs_len(n, bx.n[0] * bx.n[1] * bx.n[2]), dtype=torch.int32, device=self.dev)
                              if algo == B.PL_ALGO_RUNS else None),
                 }
                 self.parts.append({"sets": sets, **extra})

@@ -61,6 +61,7 @@ int main(void) {
   S(pl_fields) O(pl_fields, B) O(pl_fields, vg)
   S(pl_moments) O(pl_moments, J) O(pl_moments, F) O(pl_moments, eng)
   S(pl_item) O(pl_item, p) O(pl_item, f) O(pl_item, m)
+  printf("runs_len %lld\n", (long long)PL_RUNS_LEN(1000, 64));
   return 0;
 }
 """
@@ -76,7 +77,9 @@ def test_struct_layout_matches_c():
     for line in out.strip().splitlines():
         name, val = line.split()
         val = int(val)
-        if "." in name:
+        if name == "runs_len":
+            assert B.runs_len(1000, 64) == val
+        elif "." in name:
             t, f = name.split(".")
             assert getattr(getattr(B, t), f).offset == val, name
         else:

@@ -75,27 +75,39 @@ def expected_runs(sorted_keys, per_tile, ntiles):
     return out, tstart
 
 
-def expected_order(counts):
-    """Tiles with more than twice the mean run count first (by decreasing
-    count, ties by index; at most 1024 of them, the first in index order),
-    then the others in index order."""
+def expected_units(counts, split=1024, min_piece=1024, rank_max=1024):
+    """Work units of the run kernel as (tile, piece | npieces << 16) pairs.
+    With P = max(ceil(total / split), min_piece) a tile of c runs gives
+    ceil(c / P) pieces, an empty tile none; tiles cut in several pieces or
+    holding more than twice the mean run count come first (the first
+    rank_max in index order), by decreasing runs per piece then tile index,
+    then the other non-empty tiles in index order."""
+    from fractions import Fraction
     ntiles = len(counts)
-    thr = 2 * (int(counts.sum()) // max(ntiles, 1)) + 1
-    heavy = [t for t in range(ntiles) if counts[t] > thr][:1024]
-    hs = set(heavy)
-    ranked = sorted(heavy, key=lambda t: (-counts[t], t))
-    return np.array(ranked + [t for t in range(ntiles) if t not in hs], dtype=np.int64)
+    total = int(counts.sum())
+    pz = max(-(-total // split), min_piece)
+    thr = 2 * (total // max(ntiles, 1)) + 1
+    k = [-(-int(c) // pz) for c in counts]
+    cand = [t for t in range(ntiles) if k[t] >= 2 or counts[t] > thr][:rank_max]
+    cs = set(cand)
+    ranked = sorted(cand, key=lambda t: (-Fraction(int(counts[t]), k[t]), t))
+    units = []
+    for t in ranked + [t for t in range(ntiles) if t not in cs and k[t] > 0]:
+        units += [(t, p | (k[t] << 16)) for p in range(k[t])]
+    return np.array(units, dtype=np.int64).reshape(-1, 2)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_runs_table_exact(mods, prec):
     oracle, driver, inputs, B = mods
     for n, npart, tile in ((32, 8 * 32 ** 3 - 37, (8, 8, 8)), (16, 1, (4, 4, 4)), (16, 3001, (16, 8, 2)),
-                           (16, 20000, (4, 4, 4)), (32, -1, (4, 4, 4))):
+                           (16, 20000, (4, 4, 4)), (32, -1, (4, 4, 4)), (32, -2, (4, 4, 4))):
         say(f"[runs] run table {prec} n={n} np={npart} tile={tile}")
+        split = npart < 0
         if npart < 0:
-            # clumped: crowded tiles that go first in the order
-            wl = inputs.clumped_box(n=n, npart=60000, nclumps=3, sigma=1.5, steps=0)
+            # clumped: crowded tiles cut into pieces that go first in the order
+            ck = dict(npart=60000, nclumps=3, sigma=1.5) if npart == -1 else dict(npart=200000, nclumps=2, sigma=1.0)
+            wl = inputs.clumped_box(n=n, steps=0, **ck)
             npart = wl.items[0].particles.n
         else:
             wl = inputs.turbulent_box(n=n, npart=npart, steps=0)
@@ -117,13 +129,19 @@ def test_runs_table_exact(mods, prec):
         per_tile = tile[0] * tile[1] * tile[2]
         exp, tstart = expected_runs(keys[perm], per_tile, ntiles)
         assert np.array_equal(raw["tile_start"][: ntiles + 1], tstart)
-        got = raw["runs"][: npart + 2 * ntiles].astype(np.int64)
+        got = raw["runs"].astype(np.int64)
         for t in range(ntiles):
             beg = tstart[t]
             nr = exp[npart + t]
             assert got[npart + t] == nr, (t, got[npart + t], nr)
             assert np.array_equal(got[beg:beg + nr], exp[beg:beg + nr]), t
-        assert np.array_equal(got[npart + ntiles:], expected_order(exp[npart:npart + ntiles]))
+        units = expected_units(exp[npart:npart + ntiles])
+        nunits = got[npart + 3 * ntiles + 2 * B.PL_RUNS_SPLIT_UNITS]
+        say(f"  {ntiles} tiles -> {nunits} units, largest piece {np.max(exp[npart:npart + ntiles])} runs")
+        assert nunits == len(units)
+        assert np.array_equal(got[npart + ntiles:npart + ntiles + 2 * nunits].reshape(-1, 2), units)
+        if split:
+            assert (units[:, 1] >> 16).max() >= 2, "no tile was split"
         run.close()
 
 
@@ -214,6 +232,57 @@ def test_runs_drift_fp64_vs_oracle(mods):
     _assert_runs_kernel(run, B)
     _check_item(run, 0, ores[0], wl, X_TOL, 1e-11, M_TOL)
     run.close()
+
+
+def _split_box(inputs, steps=4):
+    """Two tight clumps in a 32^3 box: with 4^3 tiles the crowded tiles hold up
+    to ~8400 runs, cut into as many as 9 pieces processed by different CUs."""
+    return inputs.clumped_box(n=32, npart=200000, nclumps=2, sigma=1.0, steps=steps)
+
+
+def test_runs_split_tiles_fp64_vs_oracle(mods):
+    oracle, driver, inputs, B = mods
+    say("[runs] clumped 32^3 f64, 200000 particles, split tiles, 4 steps (sorted every 2) vs oracle")
+    wl = _split_box(inputs)
+    ores = oracle.run_workload(wl)
+    run, st = _run_gpu(driver, wl, wl.steps, True, sort_every=2, prec=B.PL_F64, algo=B.PL_ALGO_RUNS,
+                       tile=(4, 4, 4))
+    assert st == B.PL_OK
+    _assert_runs_kernel(run, B)
+    raw = run.raw(0)
+    ntiles = 8 ** 3
+    units = raw["runs"][wl.items[0].particles.n + ntiles:].astype(np.int64)
+    nunits = units[2 * (ntiles + B.PL_RUNS_SPLIT_UNITS)]
+    assert nunits > np.count_nonzero(raw["runs"][wl.items[0].particles.n:][:ntiles]), "no tile was split"
+    _check_item(run, 0, ores[0], wl, X_TOL, U_TOL, M_TOL)
+    run.close()
+
+
+def test_runs_split_tiles_f32_match_tiled(mods):
+    """Split tiles, float32 form: per-id states bit-identical to the tiled
+    kernel's, deposits within float32 rounding of it."""
+    oracle, driver, inputs, B = mods
+    say("[runs] clumped 32^3 f32, split tiles, 4 steps: runs vs tiled")
+    wl = _split_box(inputs)
+    res = {}
+    for algo in (B.PL_ALGO_TILED, B.PL_ALGO_RUNS):
+        run, st = _run_gpu(driver, wl, wl.steps, True, sort_every=2, prec=B.PL_F32_OFFSET, algo=algo,
+                           tile=(4, 4, 4), key_mode=1)
+        assert st == B.PL_OK
+        if algo == B.PL_ALGO_RUNS:
+            _assert_runs_kernel(run, B)
+        raw = run.raw(0)
+        ids = raw["id"].astype(np.int64)
+        res[algo] = ({k: _cmp.by_id(np.stack(v) if isinstance(v, list) else v, ids) for k, v in raw.items()
+                      if k in ("x", "u", "cell")}, run.moments(0))
+        run.close()
+    (sa, ma), (sb, mb) = res[B.PL_ALGO_TILED], res[B.PL_ALGO_RUNS]
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    for k in ma:
+        va, vb = np.asarray(ma[k]), np.asarray(mb[k])
+        scale = np.abs(va).max()
+        assert np.abs(va - vb).max() <= 2e-6 * scale, (k, float(np.abs(va - vb).max() / scale))
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
