@@ -18,7 +18,6 @@ on the host and are resident in HBM before the timed region starts.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import statistics
@@ -45,7 +44,6 @@ def kernel_name(cfg, B):
     return f"pl::k_step<1, 2, 3, true, 0, {ts}, {1 if ts else 0}>"
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_runs_f32_turbulent128_traffic.json")
-DIGEST_FILES = ("k_runs_impl.h", "k_runs_f32.hip", "k_step_impl.h", "pl_device.h", "pl_internal.h")
 
 
 def log(msg):
@@ -66,11 +64,8 @@ def algorithmic_bytes(prec, npart, cells, weights=True, fields=6, channels=7):
 
 
 def src_digest():
-    h = hashlib.sha256()
-    for f in DIGEST_FILES:
-        with open(os.path.join(ROOT, "paper_2602_23434_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2602_23434_amd import profiling
+    return profiling.src_digest()
 
 
 def timed_loop(run, steps, every, graph, torch, B):

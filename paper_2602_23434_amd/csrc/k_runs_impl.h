@@ -608,9 +608,14 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
     const bool do_sums = flags & SF_SUMS;
     int err = 0;
 
+    bool pre = false;                      // uniform: ctl[0] already holds the next claim
     for (;;) {
-        int g = claim_unit(counter, total_units, ctl);
-        if (g < 0) break;
+        __syncthreads();
+        if (!pre && threadIdx.x == 0) ctl[0] = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        pre = false;
+        const int g = __builtin_amdgcn_readfirstlane(ctl[0]);
+        if ((unsigned)g >= (unsigned)total_units) break;
         // item k of the launch owns units [unit_begin + k * kRunsSplit, + nunits + kRunsSplit)
         int iti = 0;
         while (iti + 1 < nitems && items[iti + 1].unit_begin + (iti + 1) * kRunsSplit <= g) ++iti;
@@ -760,8 +765,12 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
             }
         }
 
-        // flush the deposit tile: one float64 global atomic per touched cell and channel
+        // flush the deposit tile: one float64 global atomic per touched cell
+        // and channel.  The next unit is claimed first, so the claim's
+        // round trip overlaps the flush.
         __syncthreads();
+        if (threadIdx.x == 0) ctl[0] = (int)atomicAdd(counter, 1u);
+        pre = true;
         if (do_sums && threadIdx.x < 8 && S.sums[threadIdx.x] != 0.0) global_add(I.psum + threadIdx.x, S.sums[threadIdx.x]);
         {
             const int Ly = G.T[1] + 4;

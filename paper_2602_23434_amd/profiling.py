@@ -1,0 +1,155 @@
+"""rocprofv3 helpers for the headline kernel: a short counter workload and the
+summaries kept beside the sources.
+
+    python -m paper_2602_23434_amd.profiling workload [--steps 4]
+        a 256 MiB device-to-device copy (the calibration kernel), then the
+        benchmark's float32 run-based configuration on the 128^3 turbulent
+        box: one sort and `steps` fused steps, launched eagerly so that every
+        dispatch carries its own counters.  Run it under
+        `rocprofv3 --pmc FETCH_SIZE` and again under `--pmc WRITE_SIZE`.
+
+    python -m paper_2602_23434_amd.profiling trace-md DB TITLE COMMAND
+        markdown table of the top kernels of a `--kernel-trace --stats`
+        database.
+
+    python -m paper_2602_23434_amd.profiling traffic FETCH_CSV WRITE_CSV COMMAND
+        HBM bytes per launch of the run kernel as JSON: each counter's mean
+        over the kernel's dispatches, scaled by the known bytes of the copy
+        over what the same counter reads for the copy.
+
+FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch.  The JSON carries
+the digest of the kernel sources, so a reader can tell whether the figures
+still describe the built kernel.
+"""
+
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+# sources that define the float32 run kernel
+DIGEST_FILES = ("k_runs_impl.h", "k_runs_f32.hip", "k_step_impl.h", "pl_device.h", "pl_internal.h")
+COPY_BYTES = 1 << 28          # the calibration copy reads and writes 256 MiB
+COPY_ELEMS = 1 << 26         # float32 elements of the copy
+
+
+def src_digest():
+    h = hashlib.sha256()
+    for f in DIGEST_FILES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(steps=4):
+    import torch
+
+    from . import benchcfg as BC
+    from . import binding as B
+    from . import driver, inputs
+    src = torch.ones(COPY_ELEMS, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    cfg = BC.headline()
+    wl = inputs.turbulent_box(n=BC.TURB_N, npart=BC.TURB_NP, steps=steps)
+    run = driver.Run(wl, **BC.run_kwargs(cfg))
+    run.sort()
+    for _ in range(steps):
+        run.zero_moments()
+        run.step(flags=BC.STEP_FLAGS & ~B.PL_GRAPH)
+    st = run.sync()
+    stats = B.pl_part_stats(run.ctx)
+    run.close()
+    if st != B.PL_OK or stats[4] == 0 or stats[5] != 0:
+        raise RuntimeError(f"status {st}, stats {stats}")
+    print(f"profiling workload done: {steps} steps, stats {stats}", flush=True)
+
+
+def trace_md(db, title, command):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    out = [f"# {title}\n", f"Command (run from the repository root on one MI355X):\n\n```\n{command}\n```\n",
+           "Durations from `rocprofv3 --kernel-trace --stats` (top_kernels of the trace database).\n",
+           "| kernel | calls | average (ms) | total (ms) | share |", "|---|---:|---:|---:|---:|"]
+    for name, calls, tot, avg, pct in rows[:20]:
+        out.append(f"| `{name.split('(')[0]}` | {calls} | {avg / 1e3:.4f} | {tot / 1e3:.2f} | {pct:.1f}% |")
+    return "\n".join(out) + "\n"
+
+
+def _rows(path, counter):
+    with open(path) as fh:
+        return [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+
+
+def _kernel_and_copy(rows):
+    runs = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"].startswith("void pl::k_runs<")]
+    names = {r["Kernel_Name"].split("(")[0] for r in rows if r["Kernel_Name"].startswith("void pl::k_runs<")}
+    # the calibration copy: torch's device-to-device copy kernel, dispatched first
+    copy = [float(r["Counter_Value"]) for r in rows if "direct_copy_kernel" in r["Kernel_Name"]]
+    if not runs or len(names) != 1 or not copy:
+        raise RuntimeError(f"expected run-kernel dispatches of one kernel and one copy: {names}, {len(copy)}")
+    return runs, names.pop(), copy[0]
+
+
+def traffic(fetch_csv, write_csv, command):
+    fr, name, fc = _kernel_and_copy(_rows(fetch_csv, "FETCH_SIZE"))
+    wr, name2, wc = _kernel_and_copy(_rows(write_csv, "WRITE_SIZE"))
+    if name != name2:
+        raise RuntimeError(f"different kernels: {name} / {name2}")
+    f_factor = COPY_BYTES / (fc * 1024.0)
+    w_factor = COPY_BYTES / (wc * 1024.0)
+    f_kib = sum(fr) / len(fr)
+    w_kib = sum(wr) / len(wr)
+    fetch_b = f_kib * 1024.0 * f_factor
+    write_b = w_kib * 1024.0 * w_factor
+    return {
+        "kernel": name.replace("void ", ""),
+        "src_digest": src_digest(),
+        "launches": len(fr),
+        "fetch_kib_per_launch_raw": f_kib,
+        "write_kib_per_launch_raw": w_kib,
+        "copy_fetch_kib_raw": fc,
+        "copy_write_kib_raw": wc,
+        "copy_bytes": COPY_BYTES,
+        "fetch_factor": f_factor,
+        "write_factor": w_factor,
+        "fetch_bytes_per_launch": fetch_b,
+        "write_bytes_per_launch": write_b,
+        "bytes_per_launch": fetch_b + write_b,
+        "command": command,
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    w = sub.add_parser("workload")
+    w.add_argument("--steps", type=int, default=4)
+    t = sub.add_parser("trace-md")
+    t.add_argument("db")
+    t.add_argument("title")
+    t.add_argument("command")
+    c = sub.add_parser("traffic")
+    c.add_argument("fetch_csv")
+    c.add_argument("write_csv")
+    c.add_argument("command")
+    a = ap.parse_args(argv)
+    if a.cmd == "workload":
+        workload(a.steps)
+    elif a.cmd == "trace-md":
+        sys.stdout.write(trace_md(a.db, a.title, a.command))
+    else:
+        print(json.dumps(traffic(a.fetch_csv, a.write_csv, a.command), indent=1))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,44 @@
+"""The counter summary: per-launch means of the run kernel's FETCH_SIZE and
+WRITE_SIZE, scaled by the calibration copy (synthetic counter files)."""
+
+import csv
+
+import pytest
+
+from paper_2602_23434_amd import profiling
+
+FIELDS = ["Dispatch_Id", "Grid_Size", "Kernel_Name", "Counter_Name", "Counter_Value"]
+
+
+def _write(path, counter, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        for i, (name, val) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i + 1, "Grid_Size": 256, "Kernel_Name": name, "Counter_Name": counter,
+                        "Counter_Value": val})
+
+
+COPY = "void at::native::elementwise_kernel<128, 4, direct_copy_kernel_cuda lambda>(int)"
+RUNK = "void pl::k_runs<1, 2, 3, 0, 2, 1, 1>(pl::ItemDesc const*, int, int, unsigned int*, int*, unsigned int, int)"
+
+
+def test_traffic_scaling(tmp_path):
+    f, w = tmp_path / "f.csv", tmp_path / "w.csv"
+    # the copy moves 256 MiB each way; the counters see a quarter of it
+    _write(f, "FETCH_SIZE", [(COPY, 65536.0), ("pl::k_hist(int)", 5.0), (RUNK, 1000.0), (RUNK, 3000.0)])
+    _write(w, "WRITE_SIZE", [(COPY, 32768.0), (RUNK, 500.0), (RUNK, 500.0)])
+    t = profiling.traffic(str(f), str(w), "cmd")
+    assert t["kernel"] == "pl::k_runs<1, 2, 3, 0, 2, 1, 1>"
+    assert t["fetch_factor"] == pytest.approx(4.0) and t["write_factor"] == pytest.approx(8.0)
+    assert t["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 1024 * 4)
+    assert t["write_bytes_per_launch"] == pytest.approx(500.0 * 1024 * 8)
+    assert t["bytes_per_launch"] == pytest.approx(t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"])
+    assert t["launches"] == 2 and t["src_digest"] == profiling.src_digest()
+
+
+def test_traffic_needs_the_copy(tmp_path):
+    f = tmp_path / "f.csv"
+    _write(f, "FETCH_SIZE", [(RUNK, 1000.0)])
+    with pytest.raises(RuntimeError):
+        profiling.traffic(str(f), str(f), "cmd")
