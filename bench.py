@@ -253,7 +253,8 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("src_digest") == src_digest():
+        from paper_2602_23434_amd import profiling
+        if tr.get("src_digest") == src_digest() and tr.get("config") == profiling.workload_config():
             traffic = tr.get("bytes_per_launch")
     out = {
         "metric": "particle updates/sec (gather+push+deposit) and % HBM roofline, FP32 vs FP64 path",

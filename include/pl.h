@@ -81,7 +81,8 @@ typedef int pl_status;
                               read from LDS once for the run and the run's deposits are summed
                               before each LDS atomic (3D/2D, TSC/CIC, charged and dust species;
                               tracers and deposit-only calls run the PL_ALGO_TILED kernel).
-                              Needs pl_part_sort with PL_KEY_TILE_CELL, which writes p.runs */
+                              Needs pl_part_sort with PL_KEY_TILE_CELL or PL_KEY_TILE_RUN,
+                              which writes p.runs */
 
 /* Work units beyond one per tile that pl_part_sort may create by splitting
  * crowded tiles (PL_ALGO_RUNS), and the length of the run table. */
@@ -94,6 +95,11 @@ typedef int pl_status;
                                 (0 for the first in array order, ...), then by cell: consecutive
                                 particles lie in distinct cells.  Ranks of 2^rb - 1 and above share
                                 one level, rb = min(10, 32 - tile bits - cell-in-tile bits) >= 3 */
+#define PL_KEY_TILE_RUN   3  /* PL_ALGO_RUNS only: sort by tile, then by (rank in cell) / 4, then by
+                                cell, then by (rank in cell) % 4, ranks in stable tile+cell order:
+                                each run of the run table is contiguous and the runs of a tile
+                                lie in table order, so the lanes of a wave read and write one
+                                contiguous stretch of every particle array */
 
 /* flags of pl_part_gather_push / pl_part_deposit */
 #define PL_FUSE_DEPOSIT  (1u << 0)  /* gather_push also deposits at the new positions */
@@ -121,7 +127,8 @@ typedef struct {
     int prec;                        /* PL_F64 or PL_F32_OFFSET */
     int shape;                       /* PL_CIC or PL_TSC */
     int algo;                        /* PL_ALGO_PLAIN, PL_ALGO_TILED or PL_ALGO_RUNS */
-    int key_mode;                    /* PL_KEY_TILE, PL_KEY_TILE_CELL or PL_KEY_TILE_RANK */
+    int key_mode;                    /* PL_KEY_TILE, PL_KEY_TILE_CELL, PL_KEY_TILE_RANK or
+                                        PL_KEY_TILE_RUN */
     double c;                        /* speed of light in code units (> 0) */
     int nboxes;
     const pl_box_desc *boxes;        /* host array, copied */
@@ -230,7 +237,9 @@ pl_status pl_part_deposit(pl_ctx *ctx, const pl_item *items, int nitems, uint32_
  * the mean run count come first (the first 1024 such tiles in index order,
  * by decreasing runs per piece, ties by tile index), each with its pieces in
  * order, then the other non-empty tiles in index order.  Piece k of a tile
- * takes runs [c*k/npieces, c*(k+1)/npieces).
+ * takes runs [c*k/npieces, c*(k+1)/npieces).  With PL_KEY_TILE_RUN the
+ * particles of every tile are stored in run order (the runs one after another
+ * in table order from tile_start[t]) and the entries point there.
  */
 pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems);
 

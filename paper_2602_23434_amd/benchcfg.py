@@ -15,10 +15,10 @@ F64_PLAIN = dict(prec=B.PL_F64, algo=B.PL_ALGO_PLAIN, key_mode=B.PL_KEY_TILE, ti
                  channels=CHANNELS, eng=False)
 F64_TILED = dict(prec=B.PL_F64, algo=B.PL_ALGO_TILED, key_mode=B.PL_KEY_TILE_RANK, tile=(8, 8, 4), block=512,
                  channels=CHANNELS, eng=False)
-# run-based kernels (tile+cell sort, runs of up to four particles per thread)
-F32_RUNS = dict(prec=B.PL_F32_OFFSET, algo=B.PL_ALGO_RUNS, key_mode=B.PL_KEY_TILE_CELL, tile=(8, 8, 8), block=512,
+# run-based kernels (particles sorted into run order, runs of up to four particles per thread)
+F32_RUNS = dict(prec=B.PL_F32_OFFSET, algo=B.PL_ALGO_RUNS, key_mode=B.PL_KEY_TILE_RUN, tile=(8, 8, 8), block=512,
                 channels=CHANNELS, eng=False)
-F64_RUNS = dict(prec=B.PL_F64, algo=B.PL_ALGO_RUNS, key_mode=B.PL_KEY_TILE_CELL, tile=(8, 8, 4), block=512,
+F64_RUNS = dict(prec=B.PL_F64, algo=B.PL_ALGO_RUNS, key_mode=B.PL_KEY_TILE_RUN, tile=(8, 8, 4), block=512,
                 channels=CHANNELS, eng=False)
 # steps between sorts inside the timed loop when no tune file is present
 SORT_EVERY = 8

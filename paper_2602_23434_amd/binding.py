@@ -18,7 +18,7 @@ PL_F64, PL_F32_OFFSET = 0, 1
 PL_CIC, PL_TSC = 1, 2
 PL_LORENTZ, PL_DUST, PL_TRACER = 0, 1, 2
 PL_ALGO_PLAIN, PL_ALGO_TILED, PL_ALGO_RUNS = 0, 1, 2
-PL_KEY_TILE, PL_KEY_TILE_CELL, PL_KEY_TILE_RANK = 0, 1, 2
+PL_KEY_TILE, PL_KEY_TILE_CELL, PL_KEY_TILE_RANK, PL_KEY_TILE_RUN = 0, 1, 2, 3
 PL_RUNS_SPLIT_UNITS = 1024
 
 

@@ -49,7 +49,7 @@ __global__ void k_keys(SortArgs a, uint32_t *keys)
         }
         int t = c[0] / tx + ntx * (c[1] / ty + nty * (c[2] / tz));
         uint32_t key = (uint32_t)t;
-        if (a.key_mode == PL_KEY_TILE_CELL) {
+        if (a.key_mode == PL_KEY_TILE_CELL || a.key_mode == PL_KEY_TILE_RUN) {
             int loc = c[0] % tx + tx * (c[1] % ty + ty * (c[2] % tz));
             key = (uint32_t)t * (uint32_t)per_tile + (uint32_t)loc;
         }
@@ -242,10 +242,14 @@ __global__ void k_rank_keys(uint32_t *keys, int np, const int32_t *cs, int cell_
 // consecutive positions, and the runs are listed by (index of the run inside
 // its cell, cell), so consecutive runs belong to distinct cells.  Entry:
 // (first position << 2) | (length - 1), stored from runs[tile_start[t]];
-// the tile's run count goes to runs[np + t].
+// the tile's run count goes to runs[np + t].  With perm_out (run order) the
+// runs are laid out one after another in table order from tile_start[t]: the
+// entries hold those positions, and perm_out[new position] = perm_in[sorted
+// position] composes the move with the sort's permutation.
 constexpr int kRunsBuildThreads = 256;
 __global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t *keys, int np, int per_tile,
-                                                                  int ntiles, const int32_t *ts, int32_t *runs)
+                                                                  int ntiles, const int32_t *ts, int32_t *runs,
+                                                                  const uint32_t *perm_in, uint32_t *perm_out)
 {
     __shared__ int cnt[kRunsMaxTileCells];
     __shared__ int first[kRunsMaxTileCells];
@@ -280,20 +284,32 @@ __global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t
         atomicMax(&s_max, mx);
         __syncthreads();
         const int nb = s_max;
-        int base = 0;
+        int base = 0, lbase = 0;
         for (int b = 0; b < nb; ++b) {
+            // runs (high half) and particles (low half) of this round before my
+            // cells: at most 1024 runs and 4096 particles, so the halves never carry
             uint32_t here = 0;
-            for (int c = c0; c < c1; ++c) here += cnt[c] > b * kRunLen;
-            uint32_t pos = block_exclusive_scan(here, sh, total);
             for (int c = c0; c < c1; ++c) {
-                int left = cnt[c] - b * kRunLen;
+                const int left = cnt[c] - b * kRunLen;
+                if (left > 0) here += (1u << 16) | (uint32_t)min(kRunLen, left);
+            }
+            uint32_t pk = block_exclusive_scan(here, sh, total);
+            int pos = (int)(pk >> 16), lpos = (int)(pk & 0xffffu);
+            for (int c = c0; c < c1; ++c) {
+                const int left = cnt[c] - b * kRunLen;
                 if (left > 0) {
-                    int len = min(kRunLen, left);
-                    runs[beg + base + (int)pos] = ((first[c] + b * kRunLen) << 2) | (len - 1);
+                    const int len = min(kRunLen, left);
+                    const int src = first[c] + b * kRunLen;
+                    const int dst = perm_out ? beg + lbase + lpos : src;
+                    runs[beg + base + pos] = (dst << 2) | (len - 1);
+                    if (perm_out)
+                        for (int i = 0; i < len; ++i) perm_out[dst + i] = perm_in[src + i];
                     ++pos;
+                    lpos += len;
                 }
             }
-            base += (int)total;
+            base += (int)(total >> 16);
+            lbase += (int)(total & 0xffffu);
         }
         if (threadIdx.x == 0) runs[np + t] = base;
         __syncthreads();
@@ -470,9 +486,29 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
         c->stats[0] += 3;
     } else {
         hipLaunchKernelGGL(k_keys, dim3(grid_e), dim3(256), 0, s, a, c->keys[0]);
-        div = a.key_mode == PL_KEY_TILE_CELL ? per_tile_cells : 1;
+        div = a.key_mode == PL_KEY_TILE ? 1 : per_tile_cells;
         src = radix_passes(c, a.np, 0, true, bits_for((uint64_t)a.ntiles * div));
         c->stats[0]++;
+    }
+    if (a.key_mode == PL_KEY_TILE_RUN) {
+        // run order: tile offsets and the run table from the tile+cell order,
+        // then every array moved straight into run order
+        if (!a.runs) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_tile_start, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, 0, div, a.ntiles,
+                           a.tile_start);
+        hipLaunchKernelGGL(k_runs_build, dim3(std::min(a.ntiles, 8 * c->num_cu)), dim3(kRunsBuildThreads), 0, s,
+                           c->keys[src], a.np, per_tile_cells, a.ntiles, a.tile_start, a.runs,
+                           (const uint32_t *)c->idx[src], c->idx[1 - src]);
+        const uint32_t *perm = c->idx[1 - src];
+        for (int k = 0; k < a.narrays; ++k) {
+            if (a.esize[k] == 8)
+                hipLaunchKernelGGL(k_permute<8>, dim3(grid_e), dim3(256), 0, s, perm, a.np, a.src[k], a.dst[k]);
+            else
+                hipLaunchKernelGGL(k_permute<4>, dim3(grid_e), dim3(256), 0, s, perm, a.np, a.src[k], a.dst[k]);
+        }
+        hipLaunchKernelGGL(k_unit_list, dim3(1), dim3(kOrderThreads), 0, s, a.runs, a.np, a.ntiles);
+        c->stats[0] += 3 + a.narrays;
+        return hipGetLastError();
     }
     const uint32_t *perm = c->idx[src];
     for (int k = 0; k < a.narrays; ++k) {
@@ -488,7 +524,7 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
     if (a.runs) {
         // keys are tile * cells_per_tile + cell in tile (PL_KEY_TILE_CELL)
         hipLaunchKernelGGL(k_runs_build, dim3(std::min(a.ntiles, 8 * c->num_cu)), dim3(kRunsBuildThreads), 0, s,
-                           c->keys[src], a.np, per_tile_cells, a.ntiles, a.tile_start, a.runs);
+                           c->keys[src], a.np, per_tile_cells, a.ntiles, a.tile_start, a.runs, nullptr, nullptr);
         hipLaunchKernelGGL(k_unit_list, dim3(1), dim3(kOrderThreads), 0, s, a.runs, a.np, a.ntiles);
         c->stats[0] += 2;
     }

@@ -33,9 +33,12 @@ pl_status validate_desc(const pl_init_desc *d)
     if (d->prec != PL_F64 && d->prec != PL_F32_OFFSET) return PL_EINVAL;
     if (d->shape != PL_CIC && d->shape != PL_TSC) return PL_EINVAL;
     if (d->algo != PL_ALGO_PLAIN && d->algo != PL_ALGO_TILED && d->algo != PL_ALGO_RUNS) return PL_EINVAL;
-    if (d->algo == PL_ALGO_RUNS && (d->key_mode != PL_KEY_TILE_CELL || d->max_np >= (int64_t)1 << 29))
+    if (d->algo == PL_ALGO_RUNS &&
+        ((d->key_mode != PL_KEY_TILE_CELL && d->key_mode != PL_KEY_TILE_RUN) || d->max_np >= (int64_t)1 << 29))
         return PL_EINVAL;
-    if (d->key_mode != PL_KEY_TILE && d->key_mode != PL_KEY_TILE_CELL && d->key_mode != PL_KEY_TILE_RANK)
+    if (d->key_mode == PL_KEY_TILE_RUN && d->algo != PL_ALGO_RUNS) return PL_EINVAL;
+    if (d->key_mode != PL_KEY_TILE && d->key_mode != PL_KEY_TILE_CELL && d->key_mode != PL_KEY_TILE_RANK &&
+        d->key_mode != PL_KEY_TILE_RUN)
         return PL_EINVAL;
     if (!finite_pos(d->c)) return PL_EINVAL;
     if (d->nboxes < 1 || !d->boxes || d->nspecies < 1 || !d->species) return PL_EINVAL;

@@ -35,7 +35,7 @@ class Run:
         self.torch = torch
         self.wl = wl
         if key_mode is None:
-            key_mode = B.PL_KEY_TILE_CELL if algo == B.PL_ALGO_RUNS else B.PL_KEY_TILE
+            key_mode = B.PL_KEY_TILE_RUN if algo == B.PL_ALGO_RUNS else B.PL_KEY_TILE
         self.prec = prec
         self.algo = algo
         self.dev = torch.device(device)

@@ -100,6 +100,15 @@ def _kernel_and_copy(rows):
     return runs, names.pop(), copy[0]
 
 
+def workload_config():
+    """Particle order and tile of the counter workload (the benchmark's
+    headline configuration): the counters depend on them as well as on the
+    kernel sources."""
+    from . import benchcfg as BC
+    cfg = BC.headline()
+    return {"key_mode": int(cfg["key_mode"]), "tile": [int(t) for t in cfg["tile"]]}
+
+
 def traffic(fetch_csv, write_csv, command):
     fr, name, fc = _kernel_and_copy(_rows(fetch_csv, "FETCH_SIZE"))
     wr, name2, wc = _kernel_and_copy(_rows(write_csv, "WRITE_SIZE"))
@@ -114,6 +123,7 @@ def traffic(fetch_csv, write_csv, command):
     return {
         "kernel": name.replace("void ", ""),
         "src_digest": src_digest(),
+        "config": workload_config(),
         "launches": len(fr),
         "fetch_kib_per_launch_raw": f_kib,
         "write_kib_per_launch_raw": w_kib,

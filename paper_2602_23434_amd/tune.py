@@ -1,6 +1,7 @@
-"""Autotuner for the particle step: tile shape, threads per block and sort
-cadence of the run-based kernel (the tiled kernel with its rank key is timed
-beside it as a reference candidate).
+"""Autotuner for the particle step: tile shape, threads per block, particle
+order (run order or tile+cell order) and sort cadence of the run-based kernel
+(the tiled kernel with its rank key is timed beside it as a reference
+candidate).
 
     python -m paper_2602_23434_amd.tune [--f64] [--n 128 --ppc 8 --steps 32] [--out FILE]
 
@@ -36,7 +37,9 @@ def tune_file(prec):
     return os.path.join(HERE, "tune_mi355x_f32.txt" if prec == B.PL_F32_OFFSET else "tune_mi355x_f64.txt")
 
 
-def time_candidate(wl, prec, algo, tile, block, key, every, steps, torch):
+def time_candidate(wl, prec, algo, tile, block, key, every, steps, torch, reps=3):
+    """Median over `reps` timed loops of `steps` steps (the sort repeated at
+    the candidate's cadence), in ms per step; None when unsupported."""
     try:
         run = driver.Run(wl, prec=prec, algo=algo, tile=tile, block=block, key_mode=key, channels=CHANNELS,
                          eng=False)
@@ -47,15 +50,18 @@ def time_candidate(wl, prec, algo, tile, block, key, every, steps, torch):
         run.sort()
         run.step(flags=flags)
         run.sync()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(run.stream)
-        for s in range(steps):
-            if s % every == 0:
-                run.sort()
-            run.step(flags=flags)
-        e1.record(run.stream)
-        e1.synchronize()
+        times = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(run.stream)
+            for s in range(steps):
+                if s % every == 0:
+                    run.sort()
+                run.step(flags=flags)
+            e1.record(run.stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) / steps)
         st = run.sync()
         if st != B.PL_OK:
             return None
@@ -63,18 +69,21 @@ def time_candidate(wl, prec, algo, tile, block, key, every, steps, torch):
             stats = B.pl_part_stats(run.ctx)
             if stats[5] != 0:          # LDS footprint too large: the tiled kernel ran
                 return None
-        return e0.elapsed_time(e1) / steps
+        return sorted(times)[len(times) // 2]
     except B.PLError:
         return None
     finally:
         run.close()
 
 
+RUN_KEYS = [B.PL_KEY_TILE_RUN, B.PL_KEY_TILE_CELL]
+
+
 def candidates(n, prec):
-    for tile, block, every in itertools.product(TILES, RUN_BLOCKS, CADENCES):
+    for tile, block, key, every in itertools.product(TILES, RUN_BLOCKS, RUN_KEYS, CADENCES):
         if any(n % t for t in tile):
             continue
-        yield B.PL_ALGO_RUNS, tile, block, B.PL_KEY_TILE_CELL, every
+        yield B.PL_ALGO_RUNS, tile, block, key, every
     # reference: the tiled kernel with the rank-interleaved key
     tile = (8, 8, 8) if prec == B.PL_F32_OFFSET else (8, 8, 4)
     for every in CADENCES:
@@ -86,6 +95,9 @@ def tune(n=128, ppc=8, steps=32, prec=B.PL_F32_OFFSET, log=print):
     wl = inputs.turbulent_box(n=n, npart=ppc * n ** 3, steps=steps)
     best = None
     results = []
+    # one untimed pass first, so the first candidate does not pay for clocks ramping up
+    first = next(iter(candidates(n, prec)))
+    time_candidate(wl, prec, first[0], first[1], first[2], first[3], first[4], steps, torch, reps=1)
     for algo, tile, block, key, every in candidates(n, prec):
         ms = time_candidate(wl, prec, algo, tile, block, key, every, steps, torch)
         results.append({"algo": algo, "tile": tile, "block": block, "key": key, "sort_every": every, "ms": ms})

@@ -123,6 +123,8 @@ def _desc(**kw):
     dict(algo=2, key_mode=1, block=256),            # run-based block is 512
     dict(algo=2, key_mode=1, block=1024),
     dict(algo=2, key_mode=1, max_np=1 << 29),       # run entries hold the first index in 30 bits
+    dict(key_mode=3),                               # run order only with the run-based kernel
+    dict(algo=1, key_mode=3),
 ])
 def test_init_rejects_bad_descriptions(lib, bad):
     d = _desc(**bad)

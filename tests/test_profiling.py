@@ -35,6 +35,7 @@ def test_traffic_scaling(tmp_path):
     assert t["write_bytes_per_launch"] == pytest.approx(500.0 * 1024 * 8)
     assert t["bytes_per_launch"] == pytest.approx(t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"])
     assert t["launches"] == 2 and t["src_digest"] == profiling.src_digest()
+    assert t["config"] == profiling.workload_config()
 
 
 def test_traffic_needs_the_copy(tmp_path):

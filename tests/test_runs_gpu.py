@@ -97,12 +97,40 @@ def expected_units(counts, split=1024, min_piece=1024, rank_max=1024):
     return np.array(units, dtype=np.int64).reshape(-1, 2)
 
 
+def run_order(sorted_keys, per_tile):
+    """Positions of the tile+cell order in run order, from the definition of
+    PL_KEY_TILE_RUN: stable sort by (tile, rank in cell // 4, cell, rank % 4)."""
+    n = len(sorted_keys)
+    first = np.searchsorted(sorted_keys, sorted_keys, side="left")
+    rank = np.arange(n) - first
+    tile, cell = sorted_keys // per_tile, sorted_keys % per_tile
+    return np.lexsort((rank % RUN_LEN, cell, rank // RUN_LEN, tile))
+
+
+def relaid_runs(exp, tstart, npart, ntiles):
+    """The run table with every tile's runs laid out one after another in table
+    order from its first position; returns the entries and, per new position,
+    the tile+cell position it came from."""
+    out = exp.copy()
+    src = np.zeros(npart, dtype=np.int64)
+    for t in range(ntiles):
+        q = tstart[t]
+        for k in range(tstart[t], tstart[t] + exp[npart + t]):
+            first, ln = exp[k] >> 2, (exp[k] & 3) + 1
+            out[k] = (q << 2) | (ln - 1)
+            src[q:q + ln] = np.arange(first, first + ln)
+            q += ln
+    return out, src
+
+
+@pytest.mark.parametrize("key", ["cell", "run"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_runs_table_exact(mods, prec):
+def test_runs_table_exact(mods, prec, key):
     oracle, driver, inputs, B = mods
+    kmode = B.PL_KEY_TILE_CELL if key == "cell" else B.PL_KEY_TILE_RUN
     for n, npart, tile in ((32, 8 * 32 ** 3 - 37, (8, 8, 8)), (16, 1, (4, 4, 4)), (16, 3001, (16, 8, 2)),
                            (16, 20000, (4, 4, 4)), (32, -1, (4, 4, 4)), (32, -2, (4, 4, 4))):
-        say(f"[runs] run table {prec} n={n} np={npart} tile={tile}")
+        say(f"[runs] run table {prec} key {key} n={n} np={npart} tile={tile}")
         split = npart < 0
         if npart < 0:
             # clumped: crowded tiles cut into pieces that go first in the order
@@ -112,7 +140,7 @@ def test_runs_table_exact(mods, prec):
         else:
             wl = inputs.turbulent_box(n=n, npart=npart, steps=0)
         p = B.PL_F64 if prec == "f64" else B.PL_F32_OFFSET
-        run = driver.Run(wl, prec=p, algo=B.PL_ALGO_RUNS, tile=tile)
+        run = driver.Run(wl, prec=p, algo=B.PL_ALGO_RUNS, tile=tile, key_mode=kmode)
         run.sort()
         assert run.sync() == B.PL_OK
         raw = run.raw(0)
@@ -124,10 +152,14 @@ def test_runs_table_exact(mods, prec):
             cells, _ = oracle.split_positions(3, bx, x)
         keys = np.array([oracle.tile_key(3, bx, tile, 1, *cells[:, q]) for q in range(npart)], dtype=np.int64)
         perm = oracle.stable_sort_perm(keys.astype(np.uint32))
-        assert np.array_equal(raw["id"].astype(np.int64), perm)
         ntiles = (n // tile[0]) * (n // tile[1]) * (n // tile[2])
         per_tile = tile[0] * tile[1] * tile[2]
         exp, tstart = expected_runs(keys[perm], per_tile, ntiles)
+        if key == "run":
+            exp, src = relaid_runs(exp, tstart, npart, ntiles)
+            assert np.array_equal(src, run_order(keys[perm], per_tile))
+            perm = perm[src]
+        assert np.array_equal(raw["id"].astype(np.int64), perm)
         assert np.array_equal(raw["tile_start"][: ntiles + 1], tstart)
         got = raw["runs"].astype(np.int64)
         for t in range(ntiles):
@@ -192,18 +224,20 @@ def _hot_box(inputs, n=16, steps=10, dt=1.0, speed=0.6, ragged=11):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("tile", [(4, 4, 4), (8, 8, 4)])
-def test_runs_states_match_tiled_under_drift(mods, prec, tile):
+@pytest.mark.parametrize("tile,key", [((4, 4, 4), "run"), ((8, 8, 4), "run"), ((4, 4, 4), "cell")])
+def test_runs_states_match_tiled_under_drift(mods, prec, tile, key):
     """No re-sort for 10 fast steps: queues fill and overflow on the 4^3
     tiles.  Per-id states bit-identical to the tiled kernel; deposits within
-    the precision's tolerance of it."""
+    the precision's tolerance of it (run kernel on run-ordered or tile+cell
+    ordered particles)."""
     oracle, driver, inputs, B = mods
-    say(f"[runs] drift {prec} tile {tile}: runs vs tiled, 10 steps without re-sort")
+    say(f"[runs] drift {prec} tile {tile} key {key}: runs vs tiled, 10 steps without re-sort")
     wl = _hot_box(inputs)
     p = B.PL_F64 if prec == "f64" else B.PL_F32_OFFSET
     res = {}
     for algo in (B.PL_ALGO_TILED, B.PL_ALGO_RUNS):
-        run, st = _run_gpu(driver, wl, wl.steps, True, prec=p, algo=algo, tile=tile, key_mode=1)
+        kmode = B.PL_KEY_TILE_CELL if (algo == B.PL_ALGO_TILED or key == "cell") else B.PL_KEY_TILE_RUN
+        run, st = _run_gpu(driver, wl, wl.steps, True, prec=p, algo=algo, tile=tile, key_mode=kmode)
         assert st == B.PL_OK
         if algo == B.PL_ALGO_RUNS:
             _assert_runs_kernel(run, B)
@@ -266,8 +300,9 @@ def test_runs_split_tiles_f32_match_tiled(mods):
     wl = _split_box(inputs)
     res = {}
     for algo in (B.PL_ALGO_TILED, B.PL_ALGO_RUNS):
+        kmode = B.PL_KEY_TILE_CELL if algo == B.PL_ALGO_TILED else B.PL_KEY_TILE_RUN
         run, st = _run_gpu(driver, wl, wl.steps, True, sort_every=2, prec=B.PL_F32_OFFSET, algo=algo,
-                           tile=(4, 4, 4), key_mode=1)
+                           tile=(4, 4, 4), key_mode=kmode)
         assert st == B.PL_OK
         if algo == B.PL_ALGO_RUNS:
             _assert_runs_kernel(run, B)
