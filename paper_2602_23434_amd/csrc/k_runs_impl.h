@@ -379,6 +379,79 @@ __device__ __forceinline__ void batch_deposit(const UnitC<PREC> &U, const RunGeo
         }
 }
 
+// K consecutive elements of one particle array in one access.  The sort keeps
+// a run's particles consecutive, and with the run order the runs of a wave
+// follow one another, so these loads and stores cover contiguous stretches.
+// Only element alignment is known; gfx950's global accesses need dword
+// alignment.
+template <class T, int K> struct Vec {
+    typedef T V __attribute__((ext_vector_type(K)));
+    typedef __attribute__((address_space(1))) V *P;
+    typedef const __attribute__((address_space(1))) V *CP;
+};
+
+template <class T, int K>
+__device__ __forceinline__ void load_vec(gptr<const T> p, T (&out)[K])
+{
+    const typename Vec<T, K>::V v = *reinterpret_cast<typename Vec<T, K>::CP>(p);
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = v[k];
+}
+
+template <class T, int K>
+__device__ __forceinline__ void store_vec(gptr<T> p, const T (&in)[K])
+{
+    typename Vec<T, K>::V v;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = in[k];
+    *reinterpret_cast<typename Vec<T, K>::P>(p) = v;
+}
+
+// State of a whole batch (every slot handled in place) written back with one
+// access per array.
+template <int PREC, int DIM, int KR>
+__device__ __forceinline__ void store_batch(const UnitC<PREC> &U, int start, const Pos<PREC, DIM> pos[KR],
+                                            const typename RealOf<PREC>::T u[KR][3],
+                                            const typename RealOf<PREC>::T mu[KR][kMaxCh])
+{
+    using R = typename RealOf<PREC>::T;
+    R t[KR];
+    if constexpr (PREC == PL_F32_OFFSET) {
+        uint32_t cv[KR];
+#pragma unroll
+        for (int j = 0; j < KR; ++j)
+            cv[j] = pack_cell(pos[j].c[0], DIM > 1 ? pos[j].c[1] : 0, DIM > 2 ? pos[j].c[2] : 0);
+        store_vec<uint32_t, KR>(U.cell + start, cv);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+            for (int j = 0; j < KR; ++j) t[j] = pos[j].d[a];
+            store_vec<R, KR>(U.x[a] + start, t);
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+            for (int j = 0; j < KR; ++j) t[j] = pos[j].x[a];
+            store_vec<R, KR>(U.x[a] + start, t);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int j = 0; j < KR; ++j) t[j] = u[j][a];
+        store_vec<R, KR>(U.u[a] + start, t);
+    }
+    if (U.fp[0]) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int j = 0; j < KR; ++j) t[j] = mu[j][4 + a];
+            store_vec<R, KR>(U.fp[a] + start, t);
+        }
+    }
+}
+
 // Gather, push and deposit of the batch particles whose stencil lies in the
 // LDS field tile (co[j]); fb[j] is the field record of stencil point
 // (-1,-1,-1) of particle j.
@@ -391,6 +464,12 @@ __device__ __forceinline__ void batch_body(const UnitC<PREC> &U, const RunGeo &G
     constexpr int NC = FieldRec<PREC, KIND>::NC;
     constexpr int SY = Stencil<DIM>::SY, SZ = Stencil<DIM>::SZ;
     constexpr int DQ = RunsQ<PREC>::DQ;
+
+    // a batch whose slots are all handled here is written back at the end with
+    // one access per array; otherwise every slot is stored on its own
+    bool whole = true;
+#pragma unroll
+    for (int j = 0; j < KR; ++j) whole = whole && co[j];
 
     // gather and push one particle at a time (each stencil point is one
     // interleaved LDS record read); keep what the batched deposit needs
@@ -412,16 +491,19 @@ __device__ __forceinline__ void batch_body(const UnitC<PREC> &U, const RunGeo &G
         pos[j].advance(disp, U, e2);
         if (co[j]) {
             err |= e2;
-            pos[j].store(U, p);
+            if (!whole) {
+                pos[j].store(U, p);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) U.u[a][p] = u[j][a];
-            if (U.fp[0]) {
+                for (int a = 0; a < 3; ++a) U.u[a][p] = u[j][a];
+                if (U.fp[0]) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) U.fp[a][p] = mu[j][4 + a];
+                    for (int a = 0; a < 3; ++a) U.fp[a][p] = mu[j][4 + a];
+                }
             }
             if (do_sums) add_sums(S, mu[j]);
         }
     }
+    if (whole) store_batch<PREC, DIM, KR>(U, start, pos, u, mu);
 
     // deposit: the batch particles in the reference cell are summed before
     // each LDS atomic; the others are queued.  The reference is the new cell
@@ -508,6 +590,44 @@ __device__ __forceinline__ void fetch_batch(const UnitC<PREC> &U, int start, int
     using R = typename RealOf<PREC>::T;
     B.start = start;
     B.len = len;
+    if (len == KR) {
+        // a whole batch: one access per array
+        R t[KR];
+        if constexpr (PREC == PL_F32_OFFSET) {
+            uint32_t cv[KR];
+            load_vec<uint32_t, KR>((gptr<const uint32_t>)(U.cell + start), cv);
+#pragma unroll
+            for (int j = 0; j < KR; ++j) B.pr[j].cell = cv[j];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (a < DIM) load_vec<R, KR>((gptr<const R>)(U.x[a] + start), t);
+#pragma unroll
+                for (int j = 0; j < KR; ++j) B.pr[j].o[a] = a < DIM ? t[j] : 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (a < DIM) load_vec<R, KR>((gptr<const R>)(U.x[a] + start), t);
+#pragma unroll
+                for (int j = 0; j < KR; ++j) B.pr[j].x[a] = a < DIM ? t[j] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            load_vec<R, KR>((gptr<const R>)(U.u[a] + start), t);
+#pragma unroll
+            for (int j = 0; j < KR; ++j) B.u[j][a] = t[j];
+        }
+        if (U.w) {
+            load_vec<R, KR>(U.w + start, t);
+#pragma unroll
+            for (int j = 0; j < KR; ++j) B.w[j] = t[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < KR; ++j) B.w[j] = U.wdef;
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < KR; ++j) {
         const int p = start + j;
