@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 
 #include "pl_device.h"
 
@@ -195,13 +196,50 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t *keys_i
     }
 }
 
-template <int ES>
-__global__ void k_permute(const uint32_t *perm, int np, const void *src, void *dst)
+// Every SoA array of an item moved by one permutation in one pass: the
+// permutation is read once, and all of a position's loads are in flight
+// before its stores.
+struct PermArrays {
+    const void *src[SortArgs::kMaxArrays];
+    void *dst[SortArgs::kMaxArrays];
+    int wide;                // bit k: array k has 8-byte elements
+    int n;
+};
+
+__global__ void k_permute_all(const uint32_t *__restrict__ perm, int np, PermArrays pa)
 {
-    using T = typename std::conditional<ES == 8, unsigned long long, uint32_t>::type;
-    const T *s = (const T *)src;
-    T *d = (T *)dst;
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np; r += gridDim.x * blockDim.x) d[r] = s[perm[r]];
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np; r += gridDim.x * blockDim.x) {
+        const uint32_t q = perm[r];
+        unsigned long long v[SortArgs::kMaxArrays];
+#pragma unroll
+        for (int k = 0; k < SortArgs::kMaxArrays; ++k) {
+            if (k < pa.n) {
+                if ((pa.wide >> k) & 1) v[k] = ((const unsigned long long *)pa.src[k])[q];
+                else v[k] = ((const uint32_t *)pa.src[k])[q];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < SortArgs::kMaxArrays; ++k) {
+            if (k < pa.n) {
+                if ((pa.wide >> k) & 1) ((unsigned long long *)pa.dst[k])[r] = v[k];
+                else ((uint32_t *)pa.dst[k])[r] = (uint32_t)v[k];
+            }
+        }
+    }
+}
+
+static void permute_arrays(Ctx *c, const SortArgs &a, const uint32_t *perm, int grid)
+{
+    PermArrays pa;
+    memset(&pa, 0, sizeof(pa));
+    pa.n = a.narrays;
+    for (int k = 0; k < a.narrays; ++k) {
+        pa.src[k] = a.src[k];
+        pa.dst[k] = a.dst[k];
+        if (a.esize[k] == 8) pa.wide |= 1 << k;
+    }
+    hipLaunchKernelGGL(k_permute_all, dim3(grid), dim3(256), 0, c->stream, perm, a.np, pa);
+    c->stats[0]++;
 }
 
 __global__ void k_tile_start(const uint32_t *keys, int np, int shift, int per_tile, int ntiles, int32_t *ts)
@@ -499,25 +537,12 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
         hipLaunchKernelGGL(k_runs_build, dim3(std::min(a.ntiles, 8 * c->num_cu)), dim3(kRunsBuildThreads), 0, s,
                            c->keys[src], a.np, per_tile_cells, a.ntiles, a.tile_start, a.runs,
                            (const uint32_t *)c->idx[src], c->idx[1 - src]);
-        const uint32_t *perm = c->idx[1 - src];
-        for (int k = 0; k < a.narrays; ++k) {
-            if (a.esize[k] == 8)
-                hipLaunchKernelGGL(k_permute<8>, dim3(grid_e), dim3(256), 0, s, perm, a.np, a.src[k], a.dst[k]);
-            else
-                hipLaunchKernelGGL(k_permute<4>, dim3(grid_e), dim3(256), 0, s, perm, a.np, a.src[k], a.dst[k]);
-        }
+        permute_arrays(c, a, c->idx[1 - src], grid_e);
         hipLaunchKernelGGL(k_unit_list, dim3(1), dim3(kOrderThreads), 0, s, a.runs, a.np, a.ntiles);
-        c->stats[0] += 3 + a.narrays;
+        c->stats[0] += 3;
         return hipGetLastError();
     }
-    const uint32_t *perm = c->idx[src];
-    for (int k = 0; k < a.narrays; ++k) {
-        if (a.esize[k] == 8)
-            hipLaunchKernelGGL(k_permute<8>, dim3(grid_e), dim3(256), 0, s, perm, a.np, a.src[k], a.dst[k]);
-        else
-            hipLaunchKernelGGL(k_permute<4>, dim3(grid_e), dim3(256), 0, s, perm, a.np, a.src[k], a.dst[k]);
-        c->stats[0]++;
-    }
+    permute_arrays(c, a, c->idx[src], grid_e);
     hipLaunchKernelGGL(k_tile_start, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, shift, div, a.ntiles,
                        a.tile_start);
     c->stats[0]++;
