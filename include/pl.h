@@ -99,7 +99,9 @@ typedef int pl_status;
                                 cell, then by (rank in cell) % 4, ranks in stable tile+cell order:
                                 each run of the run table is contiguous and the runs of a tile
                                 lie in table order, so the lanes of a wave read and write one
-                                contiguous stretch of every particle array */
+                                contiguous stretch of every particle array.  Cells are numbered
+                                x fastest, with the rows y of every group of four (tile y size a
+                                multiple of 4) taken in the order 0, 2, 1, 3 */
 
 /* flags of pl_part_gather_push / pl_part_deposit */
 #define PL_FUSE_DEPOSIT  (1u << 0)  /* gather_push also deposits at the new positions */

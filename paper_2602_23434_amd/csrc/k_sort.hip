@@ -51,7 +51,11 @@ __global__ void k_keys(SortArgs a, uint32_t *keys)
         int t = c[0] / tx + ntx * (c[1] / ty + nty * (c[2] / tz));
         uint32_t key = (uint32_t)t;
         if (a.key_mode == PL_KEY_TILE_CELL || a.key_mode == PL_KEY_TILE_RUN) {
-            int loc = c[0] % tx + tx * (c[1] % ty + ty * (c[2] % tz));
+            int yy = c[1] % ty;
+            // run order: rows taken in the order 0, 2, 1, 3 within every group of
+            // four, so that the 16 lanes of one LDS access hold rows two apart
+            if (a.key_mode == PL_KEY_TILE_RUN && (ty & 3) == 0) yy = (yy & ~3) | ((yy & 1) << 1) | ((yy >> 1) & 1);
+            int loc = c[0] % tx + tx * (yy + ty * (c[2] % tz));
             key = (uint32_t)t * (uint32_t)per_tile + (uint32_t)loc;
         }
         keys[p] = key;

@@ -34,8 +34,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-# sources that define the float32 run kernel
-DIGEST_FILES = ("k_runs_impl.h", "k_runs_f32.hip", "k_step_impl.h", "pl_device.h", "pl_internal.h")
+# sources that define the float32 run kernel and the particle order it reads
+DIGEST_FILES = ("k_runs_impl.h", "k_runs_f32.hip", "k_step_impl.h", "pl_device.h", "pl_internal.h", "k_sort.hip")
 COPY_BYTES = 1 << 28          # the calibration copy reads and writes 256 MiB
 COPY_ELEMS = 1 << 26         # float32 elements of the copy
 

@@ -97,6 +97,19 @@ def expected_units(counts, split=1024, min_piece=1024, rank_max=1024):
     return np.array(units, dtype=np.int64).reshape(-1, 2)
 
 
+def swizzled_keys(keys, tile):
+    """Tile+cell keys with the cell numbering of PL_KEY_TILE_RUN: rows y of
+    every group of four in the order 0, 2, 1, 3 (when the tile's y size is a
+    multiple of four)."""
+    tx, ty, tz = tile
+    per_tile = tx * ty * tz
+    t, loc = keys // per_tile, keys % per_tile
+    x, y, z = loc % tx, (loc // tx) % ty, loc // (tx * ty)
+    if ty % 4 == 0:
+        y = (y // 4) * 4 + np.array([0, 2, 1, 3])[y % 4]
+    return t * per_tile + x + tx * (y + ty * z)
+
+
 def run_order(sorted_keys, per_tile):
     """Positions of the tile+cell order in run order, from the definition of
     PL_KEY_TILE_RUN: stable sort by (tile, rank in cell // 4, cell, rank % 4)."""
@@ -151,6 +164,8 @@ def test_runs_table_exact(mods, prec, key):
         else:
             cells, _ = oracle.split_positions(3, bx, x)
         keys = np.array([oracle.tile_key(3, bx, tile, 1, *cells[:, q]) for q in range(npart)], dtype=np.int64)
+        if key == "run":
+            keys = swizzled_keys(keys, tile)
         perm = oracle.stable_sort_perm(keys.astype(np.uint32))
         ntiles = (n // tile[0]) * (n // tile[1]) * (n // tile[2])
         per_tile = tile[0] * tile[1] * tile[2]
