@@ -100,8 +100,10 @@ typedef int pl_status;
                                 each run of the run table is contiguous and the runs of a tile
                                 lie in table order, so the lanes of a wave read and write one
                                 contiguous stretch of every particle array.  Cells are numbered
-                                x fastest, with the rows y of every group of four (tile y size a
-                                multiple of 4) taken in the order 0, 2, 1, 3 */
+                                x fastest, with the rows y of every group of eight taken in the
+                                order 0, 2, 4, 6, 1, 3, 5, 7 when the tile's y size is a multiple
+                                of 8, else those of every group of four in the order 0, 2, 1, 3
+                                when it is a multiple of 4 */
 
 /* flags of pl_part_gather_push / pl_part_deposit */
 #define PL_FUSE_DEPOSIT  (1u << 0)  /* gather_push also deposits at the new positions */

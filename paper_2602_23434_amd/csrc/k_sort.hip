@@ -52,9 +52,14 @@ __global__ void k_keys(SortArgs a, uint32_t *keys)
         uint32_t key = (uint32_t)t;
         if (a.key_mode == PL_KEY_TILE_CELL || a.key_mode == PL_KEY_TILE_RUN) {
             int yy = c[1] % ty;
-            // run order: rows taken in the order 0, 2, 1, 3 within every group of
-            // four, so that the 16 lanes of one LDS access hold rows two apart
-            if (a.key_mode == PL_KEY_TILE_RUN && (ty & 3) == 0) yy = (yy & ~3) | ((yy & 1) << 1) | ((yy >> 1) & 1);
+            // run order: rows taken as 0, 2, 4, 6, 1, 3, 5, 7 within every group
+            // of eight (0, 2, 1, 3 within groups of four), so that the lanes
+            // served together by one LDS access hold rows of one parity and
+            // their records and deposit cells fall on distinct banks
+            if (a.key_mode == PL_KEY_TILE_RUN && (ty & 7) == 0)
+                yy = (yy & ~7) | ((yy & 1) << 2) | ((yy >> 1) & 3);
+            else if (a.key_mode == PL_KEY_TILE_RUN && (ty & 3) == 0)
+                yy = (yy & ~3) | ((yy & 1) << 1) | ((yy >> 1) & 1);
             int loc = c[0] % tx + tx * (yy + ty * (c[2] % tz));
             key = (uint32_t)t * (uint32_t)per_tile + (uint32_t)loc;
         }

@@ -98,15 +98,20 @@ def expected_units(counts, split=1024, min_piece=1024, rank_max=1024):
 
 
 def swizzled_keys(keys, tile):
-    """Tile+cell keys with the cell numbering of PL_KEY_TILE_RUN: rows y of
-    every group of four in the order 0, 2, 1, 3 (when the tile's y size is a
-    multiple of four)."""
+    """Tile+cell keys with the cell numbering of PL_KEY_TILE_RUN: the rows y
+    of every group of eight listed as 0, 2, 4, 6, 1, 3, 5, 7 (tile y size a
+    multiple of eight), else those of every group of four as 0, 2, 1, 3 (a
+    multiple of four); the key holds each row's place in that list."""
     tx, ty, tz = tile
     per_tile = tx * ty * tz
     t, loc = keys // per_tile, keys % per_tile
     x, y, z = loc % tx, (loc // tx) % ty, loc // (tx * ty)
-    if ty % 4 == 0:
-        y = (y // 4) * 4 + np.array([0, 2, 1, 3])[y % 4]
+    if ty % 8 == 0:
+        listed = [0, 2, 4, 6, 1, 3, 5, 7]
+        y = (y // 8) * 8 + np.argsort(listed)[y % 8]
+    elif ty % 4 == 0:
+        listed = [0, 2, 1, 3]
+        y = (y // 4) * 4 + np.argsort(listed)[y % 4]
     return t * per_tile + x + tx * (y + ty * z)
 
 
