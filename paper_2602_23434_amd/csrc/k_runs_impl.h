@@ -807,14 +807,20 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
                 int gy = DIM >= 2 ? wrap_any(G.lo[1] + ly - G.hf, U.n[1]) : 0;
                 int gz = DIM >= 3 ? wrap_any(G.lo[2] + lz - G.hf, U.n[2]) : 0;
                 long gc = gx + (long)U.n[0] * (gy + (long)U.n[1] * gz);
+                // one 16-byte LDS store per 16 bytes of record (conflict-free:
+                // consecutive threads write consecutive records)
+                R v[FS];
 #pragma unroll
-                for (int q = 0; q < NC; ++q) lds_f[FR::at(e, q, G.Lf)] = (R)U.gf[q][gc];
+                for (int q = 0; q < FS; ++q) v[q] = q < NC ? (R)U.gf[q][gc] : R(0);
                 if constexpr (FR::PLANES) {
-                    lds_f[FR::at(e, 0, G.Lf) + 3] = R(0);
-                    lds_f[FR::at(e, 3, G.Lf) + 3] = R(0);
+                    *reinterpret_cast<float4 *>(lds_f + FR::at(e, 0, G.Lf)) = make_float4(v[0], v[1], v[2], 0.0f);
+                    *reinterpret_cast<float4 *>(lds_f + FR::at(e, 3, G.Lf)) = make_float4(v[3], v[4], v[5], 0.0f);
+                } else if constexpr (PREC == PL_F32_OFFSET) {
+                    *reinterpret_cast<float4 *>(lds_f + FS * e) = make_float4(v[0], v[1], v[2], v[3]);
                 } else {
 #pragma unroll
-                    for (int s = NC; s < FS; ++s) lds_f[FS * e + s] = R(0);
+                    for (int k = 0; k < FS / 2; ++k)
+                        *reinterpret_cast<double2 *>(lds_f + FS * e + 2 * k) = make_double2(v[2 * k], v[2 * k + 1]);
                 }
             }
             for (int e = threadIdx.x; e < G.Ld * nslot; e += blockDim.x) S.lds_d[e] = 0.0;
