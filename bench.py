@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--eager", action="store_true", help="launch steps without hipGraph replay")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU: the library runs on one GPU per process and has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 
