@@ -59,7 +59,7 @@ typedef int pl_status;
 #define PL_EINVAL        1   /* invalid argument (null/misaligned pointer, bad size or enum) */
 #define PL_ENOMEM        2   /* device or pinned-host allocation failed in pl_part_init */
 #define PL_EHIP          3   /* a HIP runtime call failed */
-#define PL_EUNSUPPORTED  4   /* valid request this build does not implement */
+#define PL_EUNSUPPORTED  4   /* valid request the library does not implement */
 #define PL_ECFL          5   /* a particle moved a full cell or more in one step */
 #define PL_ENONFINITE    6   /* a particle coordinate was non-finite or outside the grid */
 
