@@ -796,34 +796,69 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
         S.ctl = ctl;
         S.sums = reinterpret_cast<double *>(smem_raw + offs[5]);
 
-        // stage the field records (hf-cell halo) and clear the deposit tile
+        // stage the field records (hf-cell halo) and clear the deposit tile.
+        // Float32 form: two-deep pipeline, a record's loads are issued before
+        // the previous record is stored, and the first loads overlap the
+        // clearing.
         {
             const int Ly = G.T[1] + 2 * G.hf;
-            for (int e = threadIdx.x; e < G.Lf; e += blockDim.x) {
+            auto rec_cell = [&](int e) -> long {
                 int lx = e % G.fx;
                 int ly = (e / G.fx) % Ly;
                 int lz = e / G.fxy;
                 int gx = wrap_any(G.lo[0] + lx - G.hf, U.n[0]);
                 int gy = DIM >= 2 ? wrap_any(G.lo[1] + ly - G.hf, U.n[1]) : 0;
                 int gz = DIM >= 3 ? wrap_any(G.lo[2] + lz - G.hf, U.n[2]) : 0;
-                long gc = gx + (long)U.n[0] * (gy + (long)U.n[1] * gz);
-                // one 16-byte LDS store per 16 bytes of record (conflict-free:
-                // consecutive threads write consecutive records)
-                R v[FS];
+                return gx + (long)U.n[0] * (gy + (long)U.n[1] * gz);
+            };
+            auto rec_load = [&](int e, double (&v)[NC]) {
+                const long gc = rec_cell(e);
 #pragma unroll
-                for (int q = 0; q < FS; ++q) v[q] = q < NC ? (R)U.gf[q][gc] : R(0);
+                for (int q = 0; q < NC; ++q) v[q] = U.gf[q][gc];
+            };
+            // one 16-byte LDS store per 16 bytes of record (conflict-free:
+            // consecutive threads write consecutive records)
+            auto rec_store = [&](int e, const double (&v)[NC]) {
                 if constexpr (FR::PLANES) {
-                    *reinterpret_cast<float4 *>(lds_f + FR::at(e, 0, G.Lf)) = make_float4(v[0], v[1], v[2], 0.0f);
-                    *reinterpret_cast<float4 *>(lds_f + FR::at(e, 3, G.Lf)) = make_float4(v[3], v[4], v[5], 0.0f);
-                } else if constexpr (PREC == PL_F32_OFFSET) {
-                    *reinterpret_cast<float4 *>(lds_f + FS * e) = make_float4(v[0], v[1], v[2], v[3]);
+                    *reinterpret_cast<float4 *>(lds_f + FR::at(e, 0, G.Lf)) =
+                        make_float4((R)v[0], (R)v[1], (R)v[2], 0.0f);
+                    *reinterpret_cast<float4 *>(lds_f + FR::at(e, 3, G.Lf)) =
+                        make_float4((R)v[3], (R)v[4], (R)v[5], 0.0f);
                 } else {
+                    R w[FS];
 #pragma unroll
-                    for (int k = 0; k < FS / 2; ++k)
-                        *reinterpret_cast<double2 *>(lds_f + FS * e + 2 * k) = make_double2(v[2 * k], v[2 * k + 1]);
+                    for (int q = 0; q < FS; ++q) w[q] = q < NC ? (R)v[q] : R(0);
+                    if constexpr (PREC == PL_F32_OFFSET) {
+                        *reinterpret_cast<float4 *>(lds_f + FS * e) = make_float4(w[0], w[1], w[2], w[3]);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < FS / 2; ++k)
+                            *reinterpret_cast<double2 *>(lds_f + FS * e + 2 * k) = make_double2(w[2 * k], w[2 * k + 1]);
+                    }
                 }
+            };
+            if constexpr (PREC == PL_F32_OFFSET) {
+                double cur[NC];
+                int e = threadIdx.x;
+                if (e < G.Lf) rec_load(e, cur);
+                for (int k = threadIdx.x; k < G.Ld * nslot; k += blockDim.x) S.lds_d[k] = 0.0;
+                for (; e < G.Lf; e += blockDim.x) {
+                    double nxt[NC];
+                    const int en = e + (int)blockDim.x;
+                    if (en < G.Lf) rec_load(en, nxt);
+                    rec_store(e, cur);
+#pragma unroll
+                    for (int q = 0; q < NC; ++q) cur[q] = nxt[q];
+                }
+            } else {
+                // float64 records: one at a time (the pipeline's registers spill there)
+                for (int e = threadIdx.x; e < G.Lf; e += blockDim.x) {
+                    double v[NC];
+                    rec_load(e, v);
+                    rec_store(e, v);
+                }
+                for (int k = threadIdx.x; k < G.Ld * nslot; k += blockDim.x) S.lds_d[k] = 0.0;
             }
-            for (int e = threadIdx.x; e < G.Ld * nslot; e += blockDim.x) S.lds_d[e] = 0.0;
             if (threadIdx.x == 0) {
                 ctl[1] = 0;
                 ctl[2] = 0;
