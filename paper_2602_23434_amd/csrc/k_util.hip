@@ -64,18 +64,29 @@ __global__ void k_zero(double *p, long n)
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0.0;
 }
 
-hipError_t launch_zero(Ctx *c, const std::vector<ItemDesc> &host)
+// Every active moment channel of every item of a call in one launch: block
+// row y zeroes channel y % kMaxCh of item y / kMaxCh (items from the device
+// table of the call).
+__global__ void k_zero_items(const ItemDesc *items)
 {
-    for (const ItemDesc &it : host) {
-        if (it.kind == PL_TRACER) continue;
-        long cells = (long)it.n[0] * it.n[1] * it.n[2];
-        int grid = (int)std::min<long>((cells + 255) / 256, 8L * c->num_cu);
-        for (int ch = 0; ch < kMaxCh; ++ch) {
-            if (it.slot[ch] < 0) continue;
-            hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, c->stream, it.M[ch], cells);
-            c->stats[0]++;
-        }
-    }
+    const ItemDesc &it = items[blockIdx.y / kMaxCh];
+    const int ch = blockIdx.y % kMaxCh;
+    if (it.kind == PL_TRACER || it.slot[ch] < 0) return;
+    double *p = it.M[ch];
+    const long n = (long)it.n[0] * it.n[1] * it.n[2];
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+hipError_t launch_zero(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc> &host)
+{
+    long cells = 0;
+    for (const ItemDesc &it : host)
+        if (it.kind != PL_TRACER) cells = std::max(cells, (long)it.n[0] * it.n[1] * it.n[2]);
+    if (cells == 0 || host.empty()) return hipSuccess;
+    const int channels = (int)host.size() * kMaxCh;
+    const int gx = (int)std::max<long>(1, std::min<long>((cells + 255) / 256, (8L * c->num_cu + channels - 1) / channels * 4));
+    hipLaunchKernelGGL(k_zero_items, dim3(gx, channels), dim3(256), 0, c->stream, table);
+    c->stats[0]++;
     return hipGetLastError();
 }
 

@@ -293,7 +293,7 @@ pl_status upload_table(Ctx *c, const std::vector<ItemDesc> &host, ItemDesc *dst)
 pl_status enqueue_step(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc> &host, int total_units,
                        uint32_t flags, bool push, bool deposit)
 {
-    if (deposit && (flags & PL_ZERO_FIRST)) PL_TRY_HIP(launch_zero(c, host));
+    if (deposit && (flags & PL_ZERO_FIRST)) PL_TRY_HIP(launch_zero(c, table, host));
     if (flags & PL_SUMS) PL_TRY_HIP(launch_zero_sums(c, c->sums, 16 * c->d.max_items));
     hipError_t e = launch_step(c, table, host, (int)host.size(), total_units, flags, deposit, push);
     if (e == hipErrorInvalidConfiguration) return PL_EUNSUPPORTED;

@@ -137,7 +137,7 @@ struct Ctx {
 // Kernel launchers (k_step.hip)
 hipError_t launch_step(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc> &host, int nitems,
                        int total_units, unsigned flags, bool deposit, bool push);
-hipError_t launch_zero(Ctx *c, const std::vector<ItemDesc> &host);
+hipError_t launch_zero(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc> &host);
 hipError_t launch_zero_sums(Ctx *c, double *sums, int n);
 hipError_t launch_grid_sums(Ctx *c, const ItemDesc &it, double *out8);
 hipError_t launch_pack(Ctx *c, const ItemDesc &it, int prec, int ndim, const double *x[3], const double *u[3]);

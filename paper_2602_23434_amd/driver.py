@@ -85,6 +85,7 @@ class Run:
             self.items = (B.pl_item * len(wl.items))()
             self.parts = []
             self.moms = []
+            self.mom_blocks = []
             for i, it in enumerate(wl.items):
                 bx = wl.boxes[it.box]
                 sp = wl.species[it.species]
@@ -111,9 +112,19 @@ class Run:
                 }
                 self.parts.append({"sets": sets, **extra})
                 shape = (bx.n[2], bx.n[1], bx.n[0])
-                z = lambda: torch.zeros(shape, dtype=torch.float64, device=self.dev)
-                mo = {}
+                # every channel of the item is a view of one block, so zeroing the
+                # moments is a single fill
                 want = set(channels) if channels is not None else set(CH_NAMES)
+                if kind == B.PL_LORENTZ:
+                    nch = ("rho" in want) + 3 * ("J0" in want) + 3 * ("F0" in want) + (bool(eng) and "eng" in want)
+                elif kind == B.PL_DUST:
+                    nch = ("rho" in want) + 3 * ("F0" in want)
+                else:
+                    nch = 0
+                block = torch.zeros((nch,) + shape, dtype=torch.float64, device=self.dev)
+                used = iter(range(nch))
+                z = lambda: block[next(used)]
+                mo = {}
                 if kind == B.PL_LORENTZ:
                     if "rho" in want:
                         mo["rho"] = z()
@@ -129,6 +140,7 @@ class Run:
                     if "F0" in want:
                         mo["F"] = [z(), z(), z()]
                 self.moms.append(mo)
+                self.mom_blocks.append(block)
                 self._fill_item(i)
                 # initial state: float64 positions and velocities -> current set
                 w = torch.from_numpy(it.particles.w).to(self.dev)
@@ -251,10 +263,8 @@ class Run:
     def zero_moments(self):
         """Zero every item's moment grids on the context's stream."""
         with self.torch.cuda.stream(self.stream):
-            for mo in self.moms:
-                for v in mo.values():
-                    for t in (v if isinstance(v, list) else [v]):
-                        t.zero_()
+            for blk in self.mom_blocks:
+                blk.zero_()
 
     def close(self):
         if self.ctx:
