@@ -217,21 +217,35 @@ struct PermArrays {
 
 __global__ void k_permute_all(const uint32_t *__restrict__ perm, int np, PermArrays pa)
 {
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np; r += gridDim.x * blockDim.x) {
-        const uint32_t q = perm[r];
-        unsigned long long v[SortArgs::kMaxArrays];
+    // two positions per iteration, every load of both issued before any store
+    const int stride = gridDim.x * blockDim.x;
+    for (int r0 = blockIdx.x * blockDim.x + threadIdx.x; r0 < np; r0 += 2 * stride) {
+        const int r1 = r0 + stride;
+        const bool two = r1 < np;
+        const uint32_t q0 = perm[r0], q1 = two ? perm[r1] : q0;
+        unsigned long long v0[SortArgs::kMaxArrays], v1[SortArgs::kMaxArrays];
 #pragma unroll
         for (int k = 0; k < SortArgs::kMaxArrays; ++k) {
             if (k < pa.n) {
-                if ((pa.wide >> k) & 1) v[k] = ((const unsigned long long *)pa.src[k])[q];
-                else v[k] = ((const uint32_t *)pa.src[k])[q];
+                if ((pa.wide >> k) & 1) {
+                    v0[k] = ((const unsigned long long *)pa.src[k])[q0];
+                    v1[k] = ((const unsigned long long *)pa.src[k])[q1];
+                } else {
+                    v0[k] = ((const uint32_t *)pa.src[k])[q0];
+                    v1[k] = ((const uint32_t *)pa.src[k])[q1];
+                }
             }
         }
 #pragma unroll
         for (int k = 0; k < SortArgs::kMaxArrays; ++k) {
             if (k < pa.n) {
-                if ((pa.wide >> k) & 1) ((unsigned long long *)pa.dst[k])[r] = v[k];
-                else ((uint32_t *)pa.dst[k])[r] = (uint32_t)v[k];
+                if ((pa.wide >> k) & 1) {
+                    ((unsigned long long *)pa.dst[k])[r0] = v0[k];
+                    if (two) ((unsigned long long *)pa.dst[k])[r1] = v1[k];
+                } else {
+                    ((uint32_t *)pa.dst[k])[r0] = (uint32_t)v0[k];
+                    if (two) ((uint32_t *)pa.dst[k])[r1] = (uint32_t)v1[k];
+                }
             }
         }
     }
