@@ -1,11 +1,15 @@
 // Run-based gather -> push -> deposit kernel for gfx950 (template;
 // instantiated per precision in k_runs_f32.hip and k_runs_f64.hip).
 //
-// Work unit: one (item, cell tile).  The tile+cell sort cuts the particles of
-// every cell into runs of up to kRunLen consecutive particles and lists the
-// runs of a tile by (index of the run inside its cell, cell), so the threads
-// of a wave hold runs of distinct neighbouring cells.  A thread advances its
-// run in register batches of KR particles that share one cell:
+// Work unit: a piece of one cell tile of one item (the sort cuts a crowded
+// tile into pieces of equal run count and lists the units largest first).
+// The sort cuts the particles of every cell into runs of up to kRunLen
+// consecutive particles and lists the runs of a tile by (index of the run
+// inside its cell, cell), so the threads of a wave hold runs of distinct
+// neighbouring cells; with the run-order key the runs also lie in memory in
+// table order, so a wave's particle loads and stores are contiguous.  A
+// thread advances its run in register batches of KR particles that share one
+// cell:
 //  * every stencil point's fields are read from LDS once per batch (the
 //    components of a cell are interleaved, so one point is one or three
 //    16-byte reads) and interpolated to all particles of the batch;
@@ -13,7 +17,8 @@
 //    channel before one float64 LDS atomic, cutting LDS atomics by the run
 //    length;
 //  * the LDS deposit tile carries a two-cell halo, so particles that drifted
-//    up to one cell out of the tile since the sort still deposit into LDS.
+//    up to one cell out of the tile since the sort still deposit into LDS;
+//    the field tile does too where the LDS allows it (else one cell).
 // A particle that moved since the sort is still gathered in its batch, from
 // its own cell, while its stencil lies in the field tile; outside the tile it
 // is queued in LDS for the single-particle path.  After the push, batch
