@@ -44,6 +44,7 @@ def kernel_name(cfg, B):
     return f"pl::k_step<1, 2, 3, true, 0, {ts}, {1 if ts else 0}>"
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_runs_f32_turbulent128_traffic.json")
+INSTR_FILE = os.path.join(ROOT, "profiles", "k_runs_f32_turbulent128_instructions.json")
 
 
 def log(msg):
@@ -256,6 +257,21 @@ def main():
         from paper_2602_23434_amd import profiling
         if tr.get("src_digest") == src_digest() and tr.get("config") == profiling.workload_config():
             traffic = tr.get("bytes_per_launch")
+    # secondary ceilings (VALU issue, LDS) from the committed instruction counts
+    # of the same kernel source, measured live against this run's kernel time
+    secondary = None
+    if os.path.exists(INSTR_FILE):
+        with open(INSTR_FILE) as fh:
+            ins = json.load(fh)
+        from paper_2602_23434_amd import profiling
+        if ins.get("src_digest") == src_digest() and ins.get("config") == profiling.workload_config():
+            secondary = {
+                "valu": {"floor_ms": ins["valu_floor_ms"], "frac": ins["valu_floor_ms"] / head["kernel_ms"],
+                         "lane_insts_per_update": ins["valu_wave_insts"] * 64 / npart},
+                "lds": {"wave_insts_per_64_updates": ins["lds_wave_insts"] * 64 / npart,
+                        "bank_conflict_ms_per_cu": ins["lds_conflict_ms_per_cu"],
+                        "bank_conflict_frac": ins["lds_conflict_ms_per_cu"] / head["kernel_ms"]},
+            }
     out = {
         "metric": "particle updates/sec (gather+push+deposit) and % HBM roofline, FP32 vs FP64 path",
         "value": head["updates_per_s"],
@@ -281,6 +297,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel_name(head_cfg, B),
                      "kernel_ms": head["kernel_ms"], "alg_bytes_per_launch": head["alg_bytes"]},
+        "secondary_ceilings": secondary,
     }
     for name, key in (("f32_tiled", "fp32_tiled"), ("f64_plain", "fp64_plain"), ("f64_runs", "fp64_runs")):
         if name in results:

@@ -17,6 +17,11 @@ summaries kept beside the sources.
         over the kernel's dispatches, scaled by the known bytes of the copy
         over what the same counter reads for the copy.
 
+    python -m paper_2602_23434_amd.profiling instructions SQ_CSV COMMAND
+        VALU and LDS instruction counts per launch of the run kernel (from a
+        `rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT`
+        run of the same workload) as JSON.
+
 FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch.  The JSON carries
 the digest of the kernel sources, so a reader can tell whether the figures
 still describe the built kernel.
@@ -139,6 +144,37 @@ def traffic(fetch_csv, write_csv, command):
     }
 
 
+# chip figures for the instruction ceilings: a wave64 VALU instruction
+# occupies a 16-lane SIMD for 4 cycles
+SIMDS, CUS, CLOCK_HZ, VALU_CYCLES = 1024, 256, 2.4e9, 4
+
+
+def instructions(sq_csv, command):
+    vals = {}
+    with open(sq_csv) as fh:
+        for r in csv.DictReader(fh):
+            if r["Kernel_Name"].startswith("void pl::k_runs<"):
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+                name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+    need = ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_WAVES")
+    if not all(k in vals for k in need):
+        raise RuntimeError(f"missing counters: {sorted(vals)}")
+    mean = {k: sum(v) / len(v) for k, v in vals.items()}
+    return {
+        "kernel": name,
+        "src_digest": src_digest(),
+        "config": workload_config(),
+        "launches": len(vals["SQ_INSTS_VALU"]),
+        "valu_wave_insts": mean["SQ_INSTS_VALU"],
+        "lds_wave_insts": mean["SQ_INSTS_LDS"],
+        "lds_bank_conflict_cycles": mean["SQ_LDS_BANK_CONFLICT"],
+        "waves": mean["SQ_WAVES"],
+        "valu_floor_ms": mean["SQ_INSTS_VALU"] * VALU_CYCLES / (SIMDS * CLOCK_HZ) * 1e3,
+        "lds_conflict_ms_per_cu": mean["SQ_LDS_BANK_CONFLICT"] / CUS / CLOCK_HZ * 1e3,
+        "command": command,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -152,11 +188,16 @@ def main(argv=None):
     c.add_argument("fetch_csv")
     c.add_argument("write_csv")
     c.add_argument("command")
+    i = sub.add_parser("instructions")
+    i.add_argument("sq_csv")
+    i.add_argument("command")
     a = ap.parse_args(argv)
     if a.cmd == "workload":
         workload(a.steps)
     elif a.cmd == "trace-md":
         sys.stdout.write(trace_md(a.db, a.title, a.command))
+    elif a.cmd == "instructions":
+        print(json.dumps(instructions(a.sq_csv, a.command), indent=1))
     else:
         print(json.dumps(traffic(a.fetch_csv, a.write_csv, a.command), indent=1))
 

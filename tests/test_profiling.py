@@ -43,3 +43,21 @@ def test_traffic_needs_the_copy(tmp_path):
     _write(f, "FETCH_SIZE", [(RUNK, 1000.0)])
     with pytest.raises(RuntimeError):
         profiling.traffic(str(f), str(f), "cmd")
+
+
+def test_instruction_ceilings(tmp_path):
+    f = tmp_path / "sq.csv"
+    with open(f, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        for name, val in (("SQ_WAVES", 2048), ("SQ_INSTS_VALU", 3.0e8), ("SQ_INSTS_LDS", 4.0e7),
+                          ("SQ_LDS_BANK_CONFLICT", 1.0e8)):
+            w.writerow({"Dispatch_Id": 1, "Grid_Size": 256, "Kernel_Name": RUNK, "Counter_Name": name,
+                        "Counter_Value": val})
+            w.writerow({"Dispatch_Id": 2, "Grid_Size": 256, "Kernel_Name": COPY, "Counter_Name": name,
+                        "Counter_Value": 1.0})
+    t = profiling.instructions(str(f), "cmd")
+    assert t["valu_wave_insts"] == 3.0e8 and t["lds_wave_insts"] == 4.0e7
+    # 3e8 wave instructions x 4 cycles over 1024 SIMDs at 2.4 GHz
+    assert t["valu_floor_ms"] == pytest.approx(3.0e8 * 4 / (1024 * 2.4e9) * 1e3)
+    assert t["lds_conflict_ms_per_cu"] == pytest.approx(1.0e8 / 256 / 2.4e9 * 1e3)
