@@ -5,8 +5,8 @@ E = -v x B), 2^24 charged particles (q/m = 1, weight 1) placed uniformly with
 Maxwellian velocities (sigma = 0.05 c), TSC weights, dt = 0.05; every step
 gathers E and B, pushes (relativistic Boris) and deposits rho, J and F at the
 new positions.  The headline path is the float32 + cell-offset form with the
-run-based LDS kernel; its tile+cell sort runs inside the timed loop every
-SORT_EVERY steps.  The plain float64 path runs on the same inputs for the
+run-based LDS kernel; its sort (particles in run order: tile, run inside the
+cell, cell) runs inside the timed loop at the tuned cadence.  The plain float64 path runs on the same inputs for the
 speedup, and the run-based float64 path and the tiled float32 path beside it.
 
 Each timed step: zero the moment grids, then one fused gather/push/deposit
@@ -272,6 +272,8 @@ def main():
                         "bank_conflict_ms_per_cu": ins["lds_conflict_ms_per_cu"],
                         "bank_conflict_frac": ins["lds_conflict_ms_per_cu"] / head["kernel_ms"]},
             }
+    sort_name = {B.PL_KEY_TILE: "tile", B.PL_KEY_TILE_CELL: "tile+cell", B.PL_KEY_TILE_RANK: "tile+rank",
+                 B.PL_KEY_TILE_RUN: "run-order"}.get(head_cfg["key_mode"], str(head_cfg["key_mode"]))
     out = {
         "metric": "particle updates/sec (gather+push+deposit) and % HBM roofline, FP32 vs FP64 path",
         "value": head["updates_per_s"],
@@ -286,11 +288,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "turbulent 128^3 periodic box, 2^24 charged particles (8/cell), TSC, "
-                               "float32 + cell-offset form, run-based LDS kernel, tile+cell sort every "
+                               f"float32 + cell-offset form, run-based LDS kernel, {sort_name} sort every "
                                f"{every} steps inside the timed loop, deposit rho+J+F (inputs of the float64 "
                                "128^3 configuration)",
                    "grid": [BC.TURB_N] * 3, "particles": npart, "dt": 0.05, "shape": "tsc",
-                   "tile": list(head_cfg["tile"]), "block": head_cfg["block"], "sort_key": "tile+cell",
+                   "tile": list(head_cfg["tile"]), "block": head_cfg["block"], "sort_key": sort_name,
                    "sort_every": every, "graph": not args.eager, "reps": args.reps,
                    "ms_per_step_min": head["ms_min"], "ms_per_step_max": head["ms_max"],
                    "sort_ms": head["sort_ms"], "parallelism": "single GPU"},
