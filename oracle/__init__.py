@@ -44,7 +44,8 @@ class _Box(C.Structure):
 
 
 class _Species(C.Structure):
-    _fields_ = [("kind", C.c_int), ("q", C.c_double), ("m", C.c_double), ("t_stop", C.c_double)]
+    _fields_ = [("kind", C.c_int), ("q", C.c_double), ("m", C.c_double), ("t_stop", C.c_double),
+                ("rk", C.c_int)]
 
 
 _P = C.POINTER(C.c_double)
@@ -159,14 +160,16 @@ def step(ndim, n, shape, species, x, u, w, fields, dt, c=1.0, dx=(1.0, 1.0, 1.0)
          moments=None, abs_moments=None, fp=None, wdef=1.0):
     """Advance particle arrays x, u (3, np) float64 in place by one step.
 
-    ``species`` is (kind, q, m, t_stop).  ``fields`` maps "E","B","vg" to
+    ``species`` is (kind, q, m, t_stop[, rk]) with rk the tracers' Runge-Kutta
+    stages (2, the default, or 3).  ``fields`` maps "E","B","vg" to
     (3, nz, ny, nx) arrays (only what the kind needs).  ``moments`` and
     ``abs_moments`` are dicts from :func:`new_moments` (added to).  Returns the
     number of particles whose displacement reached one cell.
     """
-    kind, q, m, t_stop = species
+    kind, q, m, t_stop = species[:4]
+    rk = species[4] if len(species) > 4 else 2
     b = _box(ndim, n, dx)
-    sp = _Species(kind, q, m, t_stop)
+    sp = _Species(kind, q, m, t_stop, rk)
     npart = x.shape[1]
     assert x.shape == (3, npart) and u.shape == (3, npart)
     xs = (_P * 3)(*[_dp(x[d]) for d in range(3)])
@@ -288,7 +291,7 @@ def run_workload(wl, steps=None, c=1.0, abs_sums=True, fp=False):
         for _ in range(steps):
             mom = new_moments(box.n, kind)
             am = new_moments(box.n, kind) if abs_sums else None
-            viol += step(box.ndim, box.n, shape, (kind, sp.q, sp.m, sp.t_stop), x, u, w, box.fields,
+            viol += step(box.ndim, box.n, shape, (kind, sp.q, sp.m, sp.t_stop, sp.rk_stages), x, u, w, box.fields,
                          wl.dt, c=c, dx=box.dx, moments=mom, abs_moments=am, fp=fpa)
         out.append({"x": x, "u": u, "w": w, "moments": mom, "abs": am, "violations": viol, "fp": fpa})
     return out

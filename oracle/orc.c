@@ -239,6 +239,28 @@ long orc_step(const orc_box *b, int shape, double c, const orc_species *sp, long
                 xp[d] = wrap_coord(xp[d] + dt * un[d] / b->dx[d], (double)b->n[d]);
             mp[0] = sp->m * wp;                                  /* dust mass */
             for (int d = 0; d < 3; ++d) mp[4 + d] = sp->m * wp * (un[d] - uo[d]) / dt;
+        } else if (sp->rk == 3) {
+            /* Passive tracer, Eq. 1 (dx/dt = v(x)), the three-stage
+             * strong-stability-preserving Runge-Kutta scheme of Shu and Osher
+             * with the gas velocity frozen over the step:
+             *   x1 = x + dt v(x)
+             *   x2 = 3/4 x + 1/4 (x1 + dt v(x1))
+             *   x3 = 1/3 x + 2/3 (x2 + dt v(x2))
+             * written as x3 = x + dt (k1 + k2 + 4 k3)/6 with k1 = v(x),
+             * k2 = v(x + dt k1), k3 = v(x + dt (k1 + k2)/4). */
+            double k1[3], k2[3], k3[3], xs[3], h[3];
+            for (int d = 0; d < 3; ++d) k1[d] = orc_gather(b, shape, f->vg[d], xp);
+            for (int d = 0; d < 3; ++d)
+                xs[d] = (d < b->ndim) ? wrap_coord(xp[d] + dt * k1[d] / b->dx[d], (double)b->n[d]) : 0.0;
+            for (int d = 0; d < 3; ++d) k2[d] = orc_gather(b, shape, f->vg[d], xs);
+            for (int d = 0; d < 3; ++d) h[d] = 0.25 * (k1[d] + k2[d]);
+            for (int d = 0; d < 3; ++d)
+                xs[d] = (d < b->ndim) ? wrap_coord(xp[d] + dt * h[d] / b->dx[d], (double)b->n[d]) : 0.0;
+            for (int d = 0; d < 3; ++d) k3[d] = orc_gather(b, shape, f->vg[d], xs);
+            for (int d = 0; d < 3; ++d) un[d] = (k1[d] + k2[d] + 4.0 * k3[d]) / 6.0;
+            violations += moves_a_cell(b, k1, dt) | moves_a_cell(b, un, dt);
+            for (int d = 0; d < b->ndim; ++d)
+                xp[d] = wrap_coord(xp[d] + dt * un[d] / b->dx[d], (double)b->n[d]);
         } else {
             /* Passive tracer, Eq. 1 (dx/dt = v(x)), two-stage Runge-Kutta
              * (Heun) with the gas velocity frozen over the step. */

@@ -35,6 +35,7 @@ typedef struct {
     int kind;        /* ORC_LORENTZ, ORC_DUST, ORC_TRACER */
     double q, m;     /* charge and mass of one unit of weight */
     double t_stop;   /* dust stopping time */
+    int rk;          /* tracers: Runge-Kutta stages per step, 2 (Heun) or 3 (SSP, Shu and Osher) */
 } orc_species;
 
 typedef struct { const double *E[3], *B[3], *vg[3]; } orc_fields;

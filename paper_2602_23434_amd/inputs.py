@@ -148,6 +148,7 @@ class Species:
     m: float = 1.0
     weight: float = 1.0
     t_stop: float = 0.0
+    rk_stages: int = 2   # tracers: Runge-Kutta stages per step (2 or 3)
 
 
 @dataclass
