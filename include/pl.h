@@ -124,6 +124,10 @@ typedef struct {
     double q, m;      /* charge and mass per unit weight (m > 0) */
     double weight;    /* weight of every particle when an item passes no weights */
     double t_stop;    /* dust stopping time (> 0 for PL_DUST) */
+    int rk_stages;    /* PL_TRACER: Runge-Kutta stages per step with the gas velocity frozen over the
+                         step (Eq. 1): 2 (Heun; also 0) or 3 (the three-stage strong-stability-preserving
+                         scheme of Shu and Osher, the paper's third-order option, Sec. 4.1.1); ignored
+                         by the other kinds */
 } pl_species_desc;
 
 typedef struct {

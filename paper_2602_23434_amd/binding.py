@@ -40,7 +40,7 @@ class pl_box_desc(C.Structure):
 
 class pl_species_desc(C.Structure):
     _fields_ = [("kind", C.c_int), ("q", C.c_double), ("m", C.c_double), ("weight", C.c_double),
-                ("t_stop", C.c_double)]
+                ("t_stop", C.c_double), ("rk_stages", C.c_int)]
 
 
 class pl_init_desc(C.Structure):

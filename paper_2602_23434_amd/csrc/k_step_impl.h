@@ -69,7 +69,7 @@ __device__ __forceinline__ int find_item(const ItemDesc *items, int nitems, int 
 template <int PREC> struct UnitC {
     using R = typename RealOf<PREC>::T;
     int n[3];
-    int np, kind;
+    int np, kind, rk;
     R h, inv_c2, c2, q, m, wdef, inv_dt, decay, one_m_decay;
     R dtdx[3];
     double inv_dv;
@@ -96,6 +96,7 @@ __device__ __forceinline__ void load_unit(const ItemDesc &I, UnitC<PREC> &U, int
     }
     U.np = I.np;
     U.kind = I.kind;
+    U.rk = I.rk;
     U.h = (R)I.h;
     U.inv_c2 = (R)I.inv_c2;
     U.c2 = (R)I.c2;
@@ -449,23 +450,43 @@ __global__ __launch_bounds__(512, (TILED && PREC == PL_F32_OFFSET && KIND != PL_
                         for (int a = 0; a < 3; ++a) U.fp[a][p] = (R)mu[4 + a];
                     }
                 } else {
-                    // tracer: Heun's two-stage Runge-Kutta on the frozen gas velocity
+                    // tracer on the frozen gas velocity: Heun's two-stage
+                    // Runge-Kutta, or the three-stage SSP scheme of Shu and
+                    // Osher, x + dt (k1 + k2 + 4 k3) / 6 with k1 = v(x),
+                    // k2 = v(x + dt k1), k3 = v(x + dt (k1 + k2) / 4)
                     R k1[3], k2[3];
                     gather<PREC, DIM, 3>(U, lds_f, tg.L, inl, base, tg.Lx, tg.LxLy, pos.c, wx, wy, wz, k1);
-                    Pos<PREC, DIM> mid = pos;
-                    R d1[3] = {R(0), R(0), R(0)};
+                    // velocity of the stage after k, at x + dt * s (s in cells per unit time)
+                    auto stage = [&](const R s[3], R k[3]) {
+                        Pos<PREC, DIM> mid = pos;
+                        R dd[3] = {R(0), R(0), R(0)};
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) d1[a] = k1[a] * U.dtdx[a];
-                    mid.advance(d1, U, err);
-                    R dm[3] = {(R)mid.d[0], (R)mid.d[1], (R)mid.d[2]};
-                    stencil_weights<PREC, SHAPE, DIM>(dm, wx, wy, wz);
-                    int base2 = 0;
-                    bool inl2 = TILED && in_tile<DIM>(tg, mid.c, base2);
-                    gather<PREC, DIM, 3>(U, lds_f, tg.L, inl2, base2, tg.Lx, tg.LxLy, mid.c, wx, wy, wz, k2);
+                        for (int a = 0; a < DIM; ++a) dd[a] = s[a] * U.dtdx[a];
+                        mid.advance(dd, U, err);
+                        R dm[3] = {(R)mid.d[0], (R)mid.d[1], (R)mid.d[2]};
+                        R sx[3], sy[3], sz[3];
+                        stencil_weights<PREC, SHAPE, DIM>(dm, sx, sy, sz);
+                        int base2 = 0;
+                        bool inl2 = TILED && in_tile<DIM>(tg, mid.c, base2);
+                        gather<PREC, DIM, 3>(U, lds_f, tg.L, inl2, base2, tg.Lx, tg.LxLy, mid.c, sx, sy, sz, k);
+                    };
+                    stage(k1, k2);
+                    if (U.rk == 3) {
+                        R hq[3], k3[3];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        u[a] = R(0.5) * (k1[a] + k2[a]);
-                        v[a] = u[a];
+                        for (int a = 0; a < 3; ++a) hq[a] = R(0.25) * (k1[a] + k2[a]);
+                        stage(hq, k3);
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            u[a] = (k1[a] + k2[a] + R(4) * k3[a]) / R(6);
+                            v[a] = u[a];
+                        }
+                    } else {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            u[a] = R(0.5) * (k1[a] + k2[a]);
+                            v[a] = u[a];
+                        }
                     }
                 }
                 R disp[3] = {R(0), R(0), R(0)};

@@ -65,6 +65,7 @@ pl_status validate_desc(const pl_init_desc *d)
         if (p.kind != PL_LORENTZ && p.kind != PL_DUST && p.kind != PL_TRACER) return PL_EINVAL;
         if (!finite_pos(p.m) || !isfinite(p.q) || !isfinite(p.weight)) return PL_EINVAL;
         if (p.kind == PL_DUST && !finite_pos(p.t_stop)) return PL_EINVAL;
+        if (p.kind == PL_TRACER && p.rk_stages != 0 && p.rk_stages != 2 && p.rk_stages != 3) return PL_EINVAL;
     }
     return PL_OK;
 }
@@ -203,6 +204,7 @@ pl_status make_desc(const Ctx *c, const pl_item &it, double dt, Mode mode, bool 
     double dv = bx.dx[0] * bx.dx[1] * (d.ndim == 3 ? bx.dx[2] : 1.0);
     D.inv_dv = 1.0 / dv;
     D.kind = sp.kind;
+    D.rk = (sp.kind == PL_TRACER && sp.rk_stages == 3) ? 3 : 2;
     D.q = sp.q;
     D.m = sp.m;
     D.wdef = sp.weight;

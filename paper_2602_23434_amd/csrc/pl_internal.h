@@ -53,6 +53,7 @@ struct ItemDesc {
     float dtdx_f[3];
     // species
     int kind;
+    int rk;                  // tracers: Runge-Kutta stages (2 or 3)
     double h;                // (q/m) dt / 2
     double q, m, wdef;
     double decay;            // dust: exp(-dt/t_stop)

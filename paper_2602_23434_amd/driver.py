@@ -59,6 +59,7 @@ class Run:
             self._species[i].m = sp.m
             self._species[i].weight = sp.weight
             self._species[i].t_stop = sp.t_stop
+            self._species[i].rk_stages = getattr(sp, "rk_stages", 2)
         d = B.pl_init_desc()
         d.ndim = self.ndim
         d.prec = prec

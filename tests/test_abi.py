@@ -105,7 +105,7 @@ def _desc(**kw):
         if k in ("n", "tile", "dx"):
             for a in range(3):
                 getattr(boxes[0], k)[a] = v[a]
-        elif k in ("kind", "m", "t_stop", "q"):
+        elif k in ("kind", "m", "t_stop", "q", "rk_stages"):
             setattr(sp[0], k, v)
         else:
             setattr(d, k, v)
@@ -123,6 +123,7 @@ def _desc(**kw):
     dict(algo=2, key_mode=1, block=256),            # run-based block is 512
     dict(algo=2, key_mode=1, block=1024),
     dict(algo=2, key_mode=1, max_np=1 << 29),       # run entries hold the first index in 30 bits
+    dict(kind=B.PL_TRACER, rk_stages=4),            # tracers take 2 or 3 Runge-Kutta stages
     dict(key_mode=3),                               # run order only with the run-based kernel
     dict(algo=1, key_mode=3),
 ])
