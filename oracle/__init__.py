@@ -80,9 +80,6 @@ def lib():
                                C.POINTER(_Moments), C.POINTER(_Moments), C.c_void_p]
         L.orc_tile_key.restype = C.c_uint32
         L.orc_tile_key.argtypes = [C.POINTER(_Box), C.c_int * 3, C.c_int, C.c_long, C.c_long, C.c_long]
-        L.orc_keys_from_positions.restype = None
-        L.orc_keys_from_positions.argtypes = [C.POINTER(_Box), C.c_int * 3, C.c_int, C.c_long, _P * 3,
-                                              C.POINTER(C.c_uint32)]
         L.orc_split_position.restype = None
         L.orc_split_position.argtypes = [C.POINTER(_Box), _P, C.POINTER(C.c_long), C.POINTER(C.c_float)]
         L.orc_rank_keys.restype = C.c_int
@@ -201,17 +198,6 @@ def tile_key(ndim, n, tile, key_mode, i, j, k):
     b = _box(ndim, n)
     t = (C.c_int * 3)(*tile)
     return lib().orc_tile_key(C.byref(b), t, key_mode, i, j, k)
-
-
-def keys_from_positions(ndim, n, tile, key_mode, x):
-    b = _box(ndim, n)
-    t = (C.c_int * 3)(*tile)
-    npart = x.shape[1]
-    xs = (_P * 3)(*[_dp(np.ascontiguousarray(x[d])) for d in range(3)])
-    keys = np.zeros(npart, dtype=np.uint32)
-    lib().orc_keys_from_positions(C.byref(b), t, key_mode, npart, xs,
-                                  keys.ctypes.data_as(C.POINTER(C.c_uint32)))
-    return keys
 
 
 def rank_keys(ndim, n, tile, cells):

@@ -322,16 +322,6 @@ uint32_t orc_tile_key(const orc_box *b, const int tile[3], int key_mode, long i,
     return (uint32_t)(t * (long)tile[0] * tile[1] * tile[2] + local);
 }
 
-void orc_keys_from_positions(const orc_box *b, const int tile[3], int key_mode, long np,
-                             double *x[3], uint32_t *key)
-{
-    for (long p = 0; p < np; ++p) {
-        long c[3] = {0, 0, 0};
-        for (int d = 0; d < b->ndim; ++d) c[d] = (long)floor(wrap_coord(x[d][p], (double)b->n[d]));
-        key[p] = orc_tile_key(b, tile, key_mode, c[0], c[1], c[2]);
-    }
-}
-
 static int bits_for(long count)
 {
     int b = 0;

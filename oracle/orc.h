@@ -67,10 +67,6 @@ long orc_step(const orc_box *b, int shape, double c, const orc_species *sp, long
 /* Sort key of the particle in cell (i, j, k) for tiles of tile[0..2] cells. */
 uint32_t orc_tile_key(const orc_box *b, const int tile[3], int key_mode, long i, long j, long k);
 
-/* Keys of np particles from grid positions (cell = floor of each coordinate). */
-void orc_keys_from_positions(const orc_box *b, const int tile[3], int key_mode, long np,
-                             double *x[3], uint32_t *key);
-
 /* Rank-interleaved keys from cells (i, j, k) given per particle: within a tile,
  * particles are ordered first by their rank among earlier particles of the same
  * cell (0 for the first particle of a cell in array order, 1 for the second,

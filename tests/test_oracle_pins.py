@@ -446,6 +446,118 @@ def test_charge_and_momentum_conservation(orc):
     assert abs(math.fsum(mom["eng"].ravel()) - math.fsum(ep)) < 1e-10 * math.fsum(np.abs(ep))
 
 
+def test_dust_deposit_mass_and_force(orc):
+    """P6, P7, P9 for dust with q != m and cells of volume != 1: the density
+    channel carries mass (sum_cells rho dV = m sum w, not q sum w) and the
+    force channel the momentum change of the closed-form relaxation
+    v' = vg + (v - vg) exp(-dt/t_stop) in a uniform gas velocity:
+    sum_cells F dV = sum_p m w (v' - v) / dt.  The dust species deposits no
+    current and no energy."""
+    n = (8, 6, 10)
+    dx = (0.5, 0.8, 1.5)
+    dv = dx[0] * dx[1] * dx[2]
+    vg = np.array([0.07, -0.03, 0.05])
+    flds = inputs.uniform_fields(n, vg=tuple(vg))
+    rng = np.random.default_rng(21)
+    npart = 500
+    x = rng.random((3, npart)) * np.array(n)[:, None]
+    v0 = rng.normal(0.0, 0.1, (3, npart))
+    u = v0.copy()
+    wts = 0.25 + rng.random(npart)
+    q, m, ts, dt = 0.3, 2.0, 0.1, 0.05
+    mom = orc.new_moments(n, 1)
+    fp = np.zeros((3, npart))
+    orc.step(3, n, 2, (1, q, m, ts), x, u, wts, flds, dt, dx=dx, moments=mom, fp=fp)
+    assert mom["J"] is None and mom["eng"] is None
+    total = math.fsum(mom["rho"].ravel()) * dv
+    assert abs(total - m * math.fsum(wts)) < 1e-12 * m * wts.sum()
+    assert abs(total - q * math.fsum(wts)) > 0.1 * total       # mass, not charge
+    vnew = vg[:, None] + (v0 - vg[:, None]) * math.exp(-dt / ts)
+    assert np.abs(u - vnew).max() < 1e-15
+    for d in range(3):
+        fd = m * wts * (vnew[d] - v0[d]) / dt
+        assert np.abs(fp[d] - fd).max() < 1e-12 * np.abs(fd).max()
+        assert abs(math.fsum(mom["F"][d].ravel()) * dv - math.fsum(fd)) < 1e-12 * math.fsum(np.abs(fd))
+
+
+def test_deposit_time_level(orc):
+    """P4 + P8: every channel is deposited at the new position x^1.  One
+    charged particle gyrating in E = 0, B = z (q = 0.6, m = 1.3, w = 1.7): its
+    charge density equals q w times the outer product of the overlap-integral
+    weights at the closed-form x^1 = x^0 + dt u^{1/2} / gamma, with u^{1/2} the
+    old velocity turned clockwise by 2 atan(Omega dt / (2 gamma)), and its
+    current that density times v^{1/2}.  The weights at x^0 differ by far
+    more than the tolerance."""
+    n = (6, 6, 6)
+    q, m, w, dt = 0.6, 1.3, 1.7, 0.05
+    flds = inputs.uniform_fields(n)
+    x0 = np.array([2.49, 3.02, 1.51])
+    u0 = np.array([0.9, -0.6, 0.4])
+    x = x0.reshape(3, 1).copy()
+    u = u0.reshape(3, 1).copy()
+    mom = orc.new_moments(n, 0)
+    orc.step(3, n, 2, (0, q, m, 0.0), x, u, np.array([w]), flds, dt, moments=mom)
+    gam = math.sqrt(1 + u0 @ u0)
+    theta = 2 * math.atan((q / m) * dt / (2 * gam))
+    uh = np.concatenate([_rot(-theta) @ u0[:2], u0[2:]])
+    x1 = x0 + dt * uh / gam
+    assert np.abs(u[:, 0] - uh).max() < 1e-15
+    assert np.abs(x[:, 0] - x1).max() < 1e-14
+
+    def outer(xp):
+        ref = np.zeros((n[2], n[1], n[0]))
+        for k in range(-2, n[2] + 2):
+            for j in range(-2, n[1] + 2):
+                for i in range(-2, n[0] + 2):
+                    wt = (_overlap_weight(2, xp[0], i) * _overlap_weight(2, xp[1], j) *
+                          _overlap_weight(2, xp[2], k))
+                    ref[k % n[2], j % n[1], i % n[0]] += wt
+        return ref
+
+    W1, W0 = outer(x1), outer(x0)
+    assert np.abs(mom["rho"] - q * w * W1).max() < 1e-14
+    for d in range(3):
+        assert np.abs(mom["J"][d] - q * w * uh[d] / gam * W1).max() < 1e-14
+    assert np.abs(q * w * (W1 - W0)).max() > 1e-3
+
+
+def test_force_channel_boris_identity(orc):
+    """The force channel against the Boris rotation's implicit form: with
+    u- = u^{n-1/2} + h E_p, u+ = u^{n+1/2} - h E_p and gamma- = gamma(u-),
+    the rotation satisfies u+ - u- = (u+ + u-) x h B_p / gamma-, so the
+    deposited per-particle force m w (u^{n+1/2} - u^{n-1/2}) / dt equals
+    q w (E_p + vbar x B_p) with vbar = (u- + u+) / (2 gamma-), and |u+| = |u-|.
+    Turbulent fields, relativistic speeds, q != m, random weights."""
+    wl = inputs.turbulent_box(n=16, npart=2000, steps=1)
+    it = wl.items[0].particles
+    box = wl.boxes[0]
+    q, m, c, dt = 0.7, 1.9, 1.0, 0.05
+    rng = np.random.default_rng(22)
+    wts = 0.5 + rng.random(it.n)
+    x0 = it.x.copy()
+    u0 = it.u * 12.0                      # gamma up to about 3
+    x, u = x0.copy(), u0.copy()
+    fp = np.zeros((3, it.n))
+    mom = orc.new_moments(box.n, 0)
+    orc.step(3, box.n, 2, (0, q, m, 0.0), x, u, wts, box.fields, dt, c=c, moments=mom, fp=fp)
+    h = (q / m) * dt / 2
+    worst = 0.0
+    for p in range(it.n):
+        E = np.array([orc.gather(3, box.n, 2, box.fields["E"][d], x0[:, p]) for d in range(3)])
+        Bf = np.array([orc.gather(3, box.n, 2, box.fields["B"][d], x0[:, p]) for d in range(3)])
+        um = u0[:, p] + h * E
+        up = u[:, p] - h * E
+        gm = math.sqrt(1 + um @ um / c ** 2)
+        assert abs(np.linalg.norm(up) - np.linalg.norm(um)) < 1e-14 * np.linalg.norm(um)
+        vbar = (um + up) / (2 * gm)
+        ref = q * wts[p] * (E + np.cross(vbar, Bf))
+        worst = max(worst, np.abs(fp[:, p] - ref).max() / max(np.abs(ref).max(), 1e-300))
+    assert worst < 1e-12, worst
+    assert (np.sqrt(1 + (u0 * u0).sum(axis=0)) > 2.0).any()
+    for d in range(3):
+        assert abs(math.fsum(mom["F"][d].ravel()) - math.fsum(fp[d])) < 1e-12 * math.fsum(np.abs(fp[d]))
+
+
 def test_energy_work_theorem(orc):
     """The energy channel equals the work done by E: for a small step,
     m (gamma_new - gamma_old)/dt = q E . vbar with vbar the mid-step velocity;
