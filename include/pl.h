@@ -6,9 +6,11 @@
  *      fields there (the particles sample the fluid at their position, Sec. 2
  *      after Eq. 1; the weights are the textbook CIC/TSC assignment functions);
  *   2. advance it: relativistic Boris push for charged particles, exact
- *      exponential drag towards the gas velocity for dust, two-stage
- *      Runge-Kutta on the sampled gas velocity for passive tracers (Eq. 1,
- *      the paper's Lagrangian particles, two RK sub-steps per step, Sec. 3.3);
+ *      exponential drag towards the gas velocity for dust, a two- or
+ *      three-stage Runge-Kutta step on the sampled gas velocity for passive
+ *      tracers (Eq. 1, the paper's Lagrangian particles; two RK sub-steps per
+ *      step in Sec. 3.3 and Table 1, second and third order in Sec. 4.1.1;
+ *      pl_species_desc.rk_stages);
  *   3. deposit its moments (charge or mass density, current, force, energy
  *      change) onto the grid at the new position with the same weights.
  * A stable cell-tile counting sort groups particles by tile so the tiled
@@ -41,9 +43,12 @@
  * - Every call returns a pl_status.  Argument errors are detected on the host
  *   before any device work is queued and leave all data untouched.
  * - Device-side conditions (a particle that moved a full cell or more in one
- *   step, a non-finite or out-of-range particle coordinate) are latched in the
- *   context and returned by the next pl_part_sync() as PL_ECFL / PL_ENONFINITE;
- *   affected particles are still processed with wrapped, in-range indices.
+ *   step, a non-finite or out-of-range particle coordinate, an item whose
+ *   tile offsets do not describe its particles) are latched in the context
+ *   and returned by the next pl_part_sync() as PL_ECFL / PL_ENONFINITE /
+ *   PL_ENOTSORTED; particles with a bad coordinate are still processed with
+ *   wrapped, in-range indices, the particles of an unsorted item are left
+ *   untouched and deposit nothing.
  */
 #ifndef PL_H
 #define PL_H
@@ -62,6 +67,11 @@ typedef int pl_status;
 #define PL_EUNSUPPORTED  4   /* valid request the library does not implement */
 #define PL_ECFL          5   /* a particle moved a full cell or more in one step */
 #define PL_ENONFINITE    6   /* a particle coordinate was non-finite or outside the grid */
+#define PL_ENOTSORTED    7   /* PL_ALGO_TILED / PL_ALGO_RUNS met an item whose p.tile_start (or run
+                                table) does not cover its p.n particles: never sorted, sorted by a
+                                context of another algorithm, or its count changed since the sort.
+                                That item's particles were left untouched and nothing was
+                                deposited for them */
 
 /* Storage / arithmetic form of the particles. */
 #define PL_F64         0   /* float64 absolute grid coordinates and velocities */
@@ -77,10 +87,12 @@ typedef int pl_status;
 #define PL_ALGO_PLAIN 0    /* one thread per particle, fields and deposits straight from/to HBM */
 #define PL_ALGO_TILED 1    /* per-tile LDS field stage and LDS deposit (needs pl_part_sort) */
 #define PL_ALGO_RUNS  2    /* per-tile LDS kernel in which each thread advances a run of up to
-                              four particles of one cell: the fields at every stencil point are
-                              read from LDS once for the run and the run's deposits are summed
-                              before each LDS atomic (3D/2D, TSC/CIC, charged and dust species;
-                              tracers and deposit-only calls run the PL_ALGO_TILED kernel).
+                              four particles of one cell in register batches (four float32 or two
+                              float64 particles): each batch particle gathers its fields from the
+                              LDS field tile, and the batch's deposits into a stencil point are
+                              summed in registers before one LDS atomic per channel (3D/2D,
+                              TSC/CIC, charged and dust species; tracers and deposit-only calls
+                              run the PL_ALGO_TILED kernel).
                               Needs pl_part_sort with PL_KEY_TILE_CELL or PL_KEY_TILE_RUN,
                               which writes p.runs */
 
@@ -203,6 +215,10 @@ typedef struct {
  * library will ever use (sort buffers for max_np particles, item tables for
  * max_items, work counters, latched-error flags, pinned staging) and create
  * the context.  Reads tune_cache when given.  On error *out is NULL.
+ * Source: the paper's two memory rules for the particle module (Sec. 3.2):
+ * data stay resident on the device for the whole run, and allocation is kept
+ * out of the time step; here every device buffer the library needs exists
+ * from this call on, and the caller owns all particle and grid storage.
  */
 pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d);
 
@@ -210,6 +226,21 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d);
  * pl_part_gather_push: advance every particle of items[0..nitems) by one step
  * of length dt (finite, non-zero): gather at x^n, push, new position x^{n+1}
  * (periodic wrap).  Kinds, fields and channels are described above.
+ * Sources: the particles sample the fluid at their own position and tracers
+ * move with it (Sec. 2, Eq. 1; two Runge-Kutta sub-steps per step, Sec. 3.3,
+ * Table 1; second- and third-order schemes, Sec. 4.1.1).  The weights are the
+ * cloud-in-cell and triangular-shaped-cloud assignment functions of Hockney &
+ * Eastwood (Computer Simulation Using Particles, 1988, ch. 5), the same at
+ * gather and deposit.  Charged particles take the relativistic Boris push
+ * (Boris 1970: half electric kick, magnetic rotation, half kick, u^{n-1/2} ->
+ * u^{n+1/2}); dust takes the exact solution of linear drag with the gas
+ * velocity frozen over the step.  With PL_FUSE_DEPOSIT every channel is
+ * deposited at x^{n+1}, J with u^{n+1/2}, F = m w (u^{n+1/2} - u^{n-1/2})/dt.
+ * When p.fp is given it receives F of each particle, in the particle order of
+ * this call.  Items of one species kind share one persistent launch whose
+ * blocks claim (item, tile) work units from one counter; a call holding
+ * several kinds makes one launch per kind (the run-based kernel for charged
+ * and dust items, the tiled kernel for tracers).
  *   PL_FUSE_DEPOSIT  deposit the items' non-NULL moment channels at x^{n+1}
  *                    in the same pass (added to the grids' contents);
  *   PL_ZERO_FIRST    zero those channels first;
@@ -217,8 +248,8 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d);
  *   PL_GRAPH         record the launches as a hipGraph keyed by the call's
  *                    arguments and replay it on later identical calls
  *                    (the stream must not be the null stream).
- * All items go to one persistent launch per kernel stage.  Items must not
- * share particle arrays; items sharing a moment grid add into it.
+ * Items must not share particle arrays; items sharing a moment grid add into
+ * it.
  */
 pl_status pl_part_gather_push(pl_ctx *ctx, pl_item *items, int nitems, double dt, uint32_t flags);
 
@@ -226,6 +257,14 @@ pl_status pl_part_gather_push(pl_ctx *ctx, pl_item *items, int nitems, double dt
  * pl_part_deposit: deposit the current state of every item (no push): rho and
  * J from the particles, F from p.fp (required when m.F is set), eng is not
  * available here (must be NULL).  PL_ZERO_FIRST zeroes the channels first.
+ * Source: charge assignment with the same cloud-in-cell / triangular-shaped-
+ * cloud weights as the gather (Hockney & Eastwood 1988, ch. 5), so deposit
+ * is the adjoint of gather and total charge is conserved exactly; the
+ * particles are taken at their current positions.  p.fp is in the particle
+ * order of the gather_push that wrote it and a sort does not move it, so an
+ * F deposit must come before the next pl_part_sort: a deposit with m.F set
+ * after a sort of the item, with no gather_push writing p.fp in between,
+ * returns PL_EINVAL.
  */
 pl_status pl_part_deposit(pl_ctx *ctx, const pl_item *items, int nitems, uint32_t flags);
 
@@ -233,7 +272,13 @@ pl_status pl_part_deposit(pl_ctx *ctx, const pl_item *items, int nitems, uint32_
  * pl_part_sort: stable sort of each item's particles by cell-tile key (the
  * context's key_mode and the box's tile), moving every SoA array (cell, x, u,
  * w, id) from set cur into set 1-cur, writing p.tile_start, and flipping
- * items[i].p.cur.  Equal keys keep their order (bit-identical to a stable
+ * items[i].p.cur.  p.fp is not moved (see pl_part_deposit).
+ * Source: the paper stores its particles in no particular order and only
+ * compacts them (Sec. 3.2); this sort is the library's own locality step, the
+ * cell-tile sort that particle-in-cell codes use so a tile's particles are
+ * contiguous and its fields and deposits fit in on-chip memory.  It is a least
+ * significant digit radix sort (8-bit digits, stable scatter), so the
+ * permutation equals a stable comparison sort on the same keys.  Equal keys keep their order (bit-identical to a stable
  * sort).  Requires the 1-cur set for every non-NULL array of set cur.
  * With PL_ALGO_RUNS it also writes p.runs: the particles of every cell are
  * cut into runs of up to four consecutive sorted particles, and the runs of a
@@ -277,11 +322,18 @@ pl_status pl_part_sync(pl_ctx *ctx);
 /* Change the stream later work is queued on (drops recorded graphs). */
 pl_status pl_part_set_stream(pl_ctx *ctx, void *stream);
 
-/* Diagnostics, counted since pl_part_init: out[0] kernel launches, out[1]
- * graph replays, out[2] graph recordings, out[3] sorts, out[4] launches of the
- * run-based kernel, out[5] PL_ALGO_RUNS launch groups that took the tiled
- * kernel because the run-based kernel's LDS footprint exceeds the device's. */
-pl_status pl_part_stats(pl_ctx *ctx, int64_t out[6]);
+/* Diagnostics, counted since pl_part_init; writes min(n, PL_NSTATS) entries:
+ * out[0] kernel launches, out[1] graph replays, out[2] graph recordings,
+ * out[3] sorts, out[4] launches of the run-based kernel, out[5] PL_ALGO_RUNS
+ * launch groups that took the tiled kernel because the run-based kernel's
+ * LDS footprint exceeds the device's, out[6] launches of a run-based kernel
+ * compiled for a fixed tile shape and channel set, out[7] the variant of the
+ * last run-based launch: ts | chs << 4 | hf << 8, with ts the fixed tile
+ * (1: 8x8x8, 2: 8x8x4, 0: taken at run time), chs the fixed channel set
+ * (1: rho J F of charged particles, 2: rho F of dust, 0: taken at run time)
+ * and hf the field halo in cells (1 or 2). */
+#define PL_NSTATS 8
+pl_status pl_part_stats(pl_ctx *ctx, int64_t *out, int n);
 
 /* Free the context and its scratch (synchronises first).  NULL is a no-op. */
 void pl_part_finalize(pl_ctx *ctx);

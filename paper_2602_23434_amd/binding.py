@@ -13,7 +13,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpl.so")
 
-PL_OK, PL_EINVAL, PL_ENOMEM, PL_EHIP, PL_EUNSUPPORTED, PL_ECFL, PL_ENONFINITE = range(7)
+PL_OK, PL_EINVAL, PL_ENOMEM, PL_EHIP, PL_EUNSUPPORTED, PL_ECFL, PL_ENONFINITE, PL_ENOTSORTED = range(8)
+PL_NSTATS = 8
 PL_F64, PL_F32_OFFSET = 0, 1
 PL_CIC, PL_TSC = 1, 2
 PL_LORENTZ, PL_DUST, PL_TRACER = 0, 1, 2
@@ -96,7 +97,7 @@ def lib():
         L.pl_part_sums.argtypes = [_vp, P(pl_item), C.c_int, P(C.c_double)]
         L.pl_part_sync.argtypes = [_vp]
         L.pl_part_set_stream.argtypes = [_vp, _vp]
-        L.pl_part_stats.argtypes = [_vp, P(C.c_int64)]
+        L.pl_part_stats.argtypes = [_vp, P(C.c_int64), C.c_int]
         L.pl_part_finalize.argtypes = [_vp]
         L.pl_part_finalize.restype = None
         L.pl_status_string.argtypes = [C.c_int]
@@ -182,9 +183,16 @@ def pl_part_set_stream(ctx, stream):
 
 
 def pl_part_stats(ctx):
-    out = (C.c_int64 * 6)()
-    _check(lib().pl_part_stats(ctx, out), "pl_part_stats")
+    """The PL_NSTATS counters of pl_part_stats (see pl.h)."""
+    out = (C.c_int64 * PL_NSTATS)()
+    _check(lib().pl_part_stats(ctx, out, PL_NSTATS), "pl_part_stats")
     return list(out)
+
+
+def runs_variant(stats):
+    """(ts, chs, hf) of the last run-based launch from pl_part_stats' out[7]."""
+    v = int(stats[7])
+    return v & 15, (v >> 4) & 15, (v >> 8) & 15
 
 
 def pl_part_finalize(ctx):

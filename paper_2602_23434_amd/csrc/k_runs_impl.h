@@ -10,9 +10,9 @@
 // table order, so a wave's particle loads and stores are contiguous.  A
 // thread advances its run in register batches of KR particles that share one
 // cell:
-//  * every stencil point's fields are read from LDS once per batch (the
-//    components of a cell are interleaved, so one point is one or three
-//    16-byte reads) and interpolated to all particles of the batch;
+//  * each batch particle interpolates its fields from the 27 (9 in 2D)
+//    records of its own cell's stencil in the LDS field tile (one or two
+//    16-byte reads per record in float32, three in float64);
 //  * after the push, the batch's deposits are summed per stencil point and
 //    channel before one float64 LDS atomic, cutting LDS atomics by the run
 //    length;
@@ -387,10 +387,11 @@ __device__ __forceinline__ void batch_deposit(const UnitC<PREC> &U, const RunGeo
 // K consecutive elements of one particle array in one access.  The sort keeps
 // a run's particles consecutive, and with the run order the runs of a wave
 // follow one another, so these loads and stores cover contiguous stretches.
-// Only element alignment is known; gfx950's global accesses need dword
-// alignment.
+// Only element alignment is known (a batch starts at any particle), so the
+// vector type declares exactly that; gfx950's multi-dword global accesses
+// need dword alignment only.
 template <class T, int K> struct Vec {
-    typedef T V __attribute__((ext_vector_type(K)));
+    typedef T V __attribute__((ext_vector_type(K), aligned(sizeof(T))));
     typedef __attribute__((address_space(1))) V *P;
     typedef const __attribute__((address_space(1))) V *CP;
 };
@@ -749,9 +750,16 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
         const int ucap = I.nunits + kRunsSplit;
         const int local = g - ubeg;
         const int nu = min(max(I.runs[runs_count_at(I.np, I.ntiles)], 0), I.nunits > 0 ? ucap : 0);
-        if (local >= nu) {
+        // the sort's tables must cover the item's particles: tile offsets from
+        // 0 to np and at least one unit when np > 0; otherwise the item was
+        // never sorted (or its count changed since): latch it, leave it alone
+        const bool stale = I.tile_start[0] != 0 || I.tile_start[I.ntiles] != I.np || (I.np > 0 && nu == 0);
+        if (stale || local >= nu) {
             // the rest of this item's units are empty: move the counter past them
-            if (threadIdx.x == 0) atomicMax(counter, (unsigned)(ubeg + ucap));
+            if (threadIdx.x == 0) {
+                atomicMax(counter, (unsigned)(ubeg + ucap));
+                if (stale) atomicOr(errflags, (int)ERR_UNSORTED);
+            }
             continue;                                          // uniform
         }
         // the sort lists the units largest first: (tile, piece | npieces << 16)
@@ -1048,6 +1056,8 @@ hipError_t launch_runs_impl(Ctx *c, const ItemDesc *table, const ItemDesc *host,
                        (int)lds);
     c->stats[0]++;
     c->stats[4]++;
+    if (ts) c->stats[6]++;
+    c->stats[7] = ts | chs << 4 | hf << 8;
     return hipGetLastError();
 }
 

@@ -329,6 +329,12 @@ __global__ __launch_bounds__(512, (TILED && PREC == PL_F32_OFFSET && KIND != PL_
             tg.Lx = tg.T[0] + 2;
             tg.LxLy = tg.Lx * (tg.T[1] + 2);
             tg.L = tg.LxLy * (DIM >= 3 ? tg.T[2] + 2 : 1);
+            // tile offsets must run from 0 to np: otherwise the item was never
+            // sorted (or its count changed since): latch it, leave it alone
+            if (I.tile_start[0] != 0 || I.tile_start[I.ntiles] != I.np) {
+                if (threadIdx.x == 0) atomicOr(errflags, (int)ERR_UNSORTED);
+                continue;                  // uniform
+            }
             int a = I.tile_start[t], b = I.tile_start[t + 1];
             pbeg = min(max(a, 0), I.np);
             pend = min(max(b, pbeg), I.np);

@@ -190,6 +190,8 @@ pl_status make_desc(const Ctx *c, const pl_item &it, double dt, Mode mode, bool 
     if (mode == MODE_DEPOSIT) {
         if (m.eng) return PL_EINVAL;
         if (nF && nfp != 3) return PL_EINVAL;
+        if (nF && std::find(c->fp_stale.begin(), c->fp_stale.end(), (const void *)p.fp[0]) != c->fp_stale.end())
+            return PL_EINVAL;
     }
 
     memset(&D, 0, sizeof(D));
@@ -321,6 +323,13 @@ pl_status run_call(Ctx *c, const pl_item *items, int nitems, double dt, uint32_t
     int total = 0;
     pl_status st = build_table(c, items, nitems, dt, mode, deposit, host, total);
     if (st != PL_OK) return st;
+    if (push) {
+        // this step rewrites p.fp in the items' current order
+        for (int i = 0; i < nitems; ++i) {
+            auto it = std::find(c->fp_stale.begin(), c->fp_stale.end(), (const void *)items[i].p.fp[0]);
+            if (it != c->fp_stale.end()) c->fp_stale.erase(it);
+        }
+    }
 
     if (!(flags & PL_GRAPH)) {
         st = upload_table(c, host, c->table);
@@ -403,6 +412,7 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d)
     c->d.species = c->species.data();
     c->stream = (hipStream_t)d->stream;
     c->max_np = d->max_np;
+    c->fp_stale.reserve(4 * (size_t)d->max_items + 16);
 
     int tuned_block = 256, tuned_tile[3] = {8, 8, 8}, tuned_runs = 0, tuned_runs_block = 512;
     if (d->prec == PL_F64 && d->algo == PL_ALGO_TILED) { tuned_tile[1] = 4; tuned_tile[2] = 4; }
@@ -550,6 +560,12 @@ pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems)
         if (launch_sort(c, args[i]) != hipSuccess) return PL_EHIP;
         items[i].p.cur = 1 - items[i].p.cur;
         c->stats[3]++;
+        const void *fp = items[i].p.fp[0];
+        if (fp && std::find(c->fp_stale.begin(), c->fp_stale.end(), fp) == c->fp_stale.end()) {
+            // bounded: the oldest entry goes first
+            if (c->fp_stale.size() >= c->fp_stale.capacity()) c->fp_stale.erase(c->fp_stale.begin());
+            c->fp_stale.push_back(fp);
+        }
     }
     return PL_OK;
 }
@@ -618,6 +634,7 @@ pl_status pl_part_sync(pl_ctx *ctx)
     int flags = 0;
     PL_TRY_HIP(hipMemcpy(&flags, c->errflags, sizeof(int), hipMemcpyDeviceToHost));
     if (flags) PL_TRY_HIP(hipMemset(c->errflags, 0, sizeof(int)));
+    if (flags & ERR_UNSORTED) return PL_ENOTSORTED;
     if (flags & ERR_NONFINITE) return PL_ENONFINITE;
     if (flags & ERR_CFL) return PL_ECFL;
     return PL_OK;
@@ -639,11 +656,11 @@ pl_status pl_part_set_stream(pl_ctx *ctx, void *stream)
     return PL_OK;
 }
 
-pl_status pl_part_stats(pl_ctx *ctx, int64_t out[6])
+pl_status pl_part_stats(pl_ctx *ctx, int64_t *out, int n)
 {
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
-    if (!c || !out) return PL_EINVAL;
-    for (int k = 0; k < 6; ++k) out[k] = c->stats[k];
+    if (!c || !out || n < 0) return PL_EINVAL;
+    for (int k = 0; k < n && k < PL_NSTATS; ++k) out[k] = c->stats[k];
     return PL_OK;
 }
 
@@ -665,6 +682,7 @@ const char *pl_status_string(pl_status s)
     case PL_EUNSUPPORTED: return "unsupported request";
     case PL_ECFL: return "a particle moved a full cell or more in one step";
     case PL_ENONFINITE: return "non-finite or out-of-range particle coordinate";
+    case PL_ENOTSORTED: return "an item's tile offsets or run table do not cover its particles (sort it first)";
     default: return "unknown status";
     }
 }

@@ -29,7 +29,7 @@ __host__ __device__ inline int64_t runs_count_at(int64_t np, int ntiles)
 enum Channel { CH_RHO = 0, CH_J0 = 1, CH_F0 = 4, CH_ENG = 7 };
 
 // Latched device-side error bits.
-enum ErrBit { ERR_CFL = 1, ERR_NONFINITE = 2 };
+enum ErrBit { ERR_CFL = 1, ERR_NONFINITE = 2, ERR_UNSORTED = 4 };
 
 // Mode bits of the step kernels.
 enum StepFlag : unsigned {
@@ -131,8 +131,14 @@ struct Ctx {
     GraphEntry graphs[kGraphs];
     uint64_t use_clock = 0;
 
-    int64_t stats[6] = {0, 0, 0, 0, 0, 0}; // launches, graph replays, graph captures, sorts,
-                                           // run-kernel launches, run groups on the tiled kernel
+    // launches, graph replays, graph captures, sorts, run-kernel launches, run
+    // groups on the tiled kernel, fixed-shape run-kernel launches, variant of
+    // the last run-kernel launch (pl.h, pl_part_stats)
+    int64_t stats[PL_NSTATS] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+    // p.fp arrays whose particles a sort has reordered since a gather_push
+    // last wrote them: a deposit of F from them is refused
+    std::vector<const void *> fp_stale;
 };
 
 // Kernel launchers (k_step.hip)

@@ -39,8 +39,9 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_status_strings(lib):
-    for s in range(7):
+    for s in range(8):
         assert B.pl_status_string(s) not in ("", "unknown status")
+    assert "sort" in B.pl_status_string(B.PL_ENOTSORTED)
     assert B.pl_status_string(99) == "unknown status"
 
 
@@ -150,5 +151,7 @@ def test_null_context_calls_are_rejected(lib):
     assert lib.pl_part_deposit(None, C.byref(item), 1, 0) == B.PL_EINVAL
     assert lib.pl_part_sort(None, C.byref(item), 1) == B.PL_EINVAL
     assert lib.pl_part_sync(None) == B.PL_EINVAL
+    out = (C.c_int64 * B.PL_NSTATS)()
+    assert lib.pl_part_stats(None, out, B.PL_NSTATS) == B.PL_EINVAL
     assert lib.pl_part_init(None, None) == B.PL_EINVAL
     lib.pl_part_finalize(None)

@@ -1,0 +1,191 @@
+"""Whole-grid oracle parity of the exact kernel variants the benchmark times,
+and the device-side check that an item was sorted.
+
+The benchmark's float32 path runs the run-based kernel compiled for 8^3
+tiles, the rho+J+F channel set and a two-cell field halo; its float64 path
+the one compiled for 8x8x4 tiles and the same channels.  Here both run on a
+32^3 turbulent box (64 tiles, 8 particles per cell less a ragged tail) for
+20 steps with a sort every 8 steps, as in the benchmark, and every particle
+and every cell is compared with the float64 oracle.  pl_part_stats reports
+which variant ran, so the tests prove they checked the benchmarked code.
+
+Tolerances.  Float64: positions 1e-11 cells, velocities 1e-12 * max(|u|,
+sigma), deposits 1e-12 * A_c (A_c = sum over particles of |mu| W: the scale
+of the summation round-off of that cell).  Float32 form: the error table
+(max and RMS, per position and velocity component and per deposited
+channel) is bounded by tests/_cmp.py's FP32_BOUNDS, frozen at twice the
+values this test measured on MI355X (rounded up); the measured table is
+written to gpurun_out/ when that folder exists.
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from tests import _cmp
+from tests.test_parity_gpu import M_TOL, U_TOL, X_TOL, _check_item
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    from paper_2602_23434_amd import binding, driver, inputs
+    binding.lib()
+    return oracle, driver, inputs, binding
+
+
+@pytest.fixture(scope="module")
+def turb32(mods):
+    oracle, driver, inputs, B = mods
+    wl = inputs.turbulent_box(n=32, npart=8 * 32 ** 3 - 37, steps=20)
+    return wl, oracle.run_workload(wl)
+
+
+def _bench_run(driver, B, wl, cfg, every):
+    from paper_2602_23434_amd import benchcfg as BC
+    run = driver.Run(wl, **BC.run_kwargs(cfg))
+    for s in range(wl.steps):
+        if s % every == 0:
+            run.sort()
+        run.step(flags=BC.STEP_FLAGS)
+    assert run.sync() == B.PL_OK
+    return run
+
+
+def test_bench_variant_f64_whole_grid(mods, turb32):
+    oracle, driver, inputs, B = mods
+    from paper_2602_23434_amd import benchcfg as BC
+    wl, ores = turb32
+    say("[variants] f64 run kernel, 8x8x4 tiles, rho J F, 32^3, 20 steps, sort every 8, vs oracle")
+    run = _bench_run(driver, B, wl, BC.F64_RUNS, BC.SORT_EVERY)
+    st = B.pl_part_stats(run.ctx)
+    assert st[4] > 0 and st[5] == 0 and st[6] == st[4], st
+    assert B.runs_variant(st) == (2, 1, 2), B.runs_variant(st)
+    ex, eu, errs = _check_item(run, 0, ores[0], wl, X_TOL, U_TOL, M_TOL, eng=False)
+    assert set(errs) == {"rho", "J0", "J1", "J2", "F0", "F1", "F2"}, errs.keys()
+    say(f"  x {ex:.2e} u {eu:.2e} " + " ".join(f"{k}:{v[0]:.1e}" for k, v in errs.items()))
+    run.close()
+
+
+def test_bench_variant_f32_whole_grid(mods, turb32):
+    oracle, driver, inputs, B = mods
+    from paper_2602_23434_amd import benchcfg as BC
+    wl, ores = turb32
+    say("[variants] f32 run kernel, 8^3 tiles, rho J F, 32^3, 20 steps, sort every 8, vs oracle")
+    run = _bench_run(driver, B, wl, BC.F32_RUNS, BC.SORT_EVERY)
+    st = B.pl_part_stats(run.ctx)
+    assert st[4] > 0 and st[5] == 0 and st[6] == st[4], st
+    assert B.runs_variant(st) == (1, 1, 2), B.runs_variant(st)
+    gx, gu, gid, _ = run.state(0)
+    table = _cmp.state_error_stats(gx, gu, gid, ores[0]["x"], ores[0]["u"], wl.boxes[0].n, 3)
+    merr = _cmp.moment_errors(run.moments(0), ores[0]["moments"], ores[0]["abs"])
+    assert set(merr) == {"rho", "J0", "J1", "J2", "F0", "F1", "F2"}, merr.keys()
+    out = {"workload": "turbulent 32^3, 262107 particles, 20 steps, sort every 8, float32 run kernel "
+                       "(8^3 tiles, rho J F) vs float64 oracle, every particle and cell",
+           "units": "x: cells; u: |du|/max(|u|, 0.05) per component; deposits: |dM|/A_c per cell",
+           "table": {}}
+    for k, (mx, rms) in table.items():
+        say(f"  {k:4s} max {mx:.3e} rms {rms:.3e}")
+        out["table"][k] = {"max": mx, "rms": rms}
+    for k, (mx, rms, rel) in merr.items():
+        say(f"  {k:4s} max/A_c {mx:.3e} rms/A_c {rms:.3e} max/max|M| {rel:.3e}")
+        out["table"][k] = {"max": mx, "rms": rms, "max_over_max_abs": rel}
+    gdir = os.path.join(ROOT, "gpurun_out")
+    if os.path.isdir(gdir):
+        with open(os.path.join(gdir, "f32_error_table_turbulent32.json"), "w") as f:
+            json.dump(out, f, indent=1)
+    bad = _cmp.check_fp32_table(table, merr)
+    assert not bad, bad
+    run.close()
+
+
+# ---------------------------------------------------------------- unsorted items
+
+def _snapshot(run):
+    raw = run.raw(0)
+    return {k: (np.stack(v) if isinstance(v, list) else v).copy() for k, v in raw.items()
+            if k in ("cell", "x", "u")}
+
+
+@pytest.mark.parametrize("prec,algo", [("f32", "runs"), ("f64", "runs"), ("f32", "tiled")])
+def test_unsorted_item_is_latched(mods, prec, algo):
+    """A tiled or run-based step on an item that was never sorted, or whose
+    count changed since its sort, latches PL_ENOTSORTED and leaves the
+    particles as they were; after a sort the same call succeeds."""
+    oracle, driver, inputs, B = mods
+    say(f"[variants] unsorted item latched: {prec} {algo}")
+    wl = inputs.turbulent_box(n=16, npart=8 * 16 ** 3 - 5, steps=1)
+    p = B.PL_F64 if prec == "f64" else B.PL_F32_OFFSET
+    a = B.PL_ALGO_RUNS if algo == "runs" else B.PL_ALGO_TILED
+    run = driver.Run(wl, prec=p, algo=a)
+    before = _snapshot(run)
+    assert run.step() == B.PL_OK            # arguments are fine; the device finds no sort
+    assert run.sync() == B.PL_ENOTSORTED
+    after = _snapshot(run)
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+    assert np.abs(run.moments(0)["rho"]).max() == 0.0
+    assert run.sync() == B.PL_OK             # the latch was cleared
+    run.sort()
+    run.step()
+    assert run.sync() == B.PL_OK
+    moved = _snapshot(run)
+    assert not np.array_equal(moved["u"], after["u"])
+    # a count that no longer matches the sort
+    n = run.items[0].p.n
+    run.items[0].p.n = n - 3
+    run.step()
+    assert run.sync() == B.PL_ENOTSORTED
+    run.items[0].p.n = n
+    run.step()
+    assert run.sync() == B.PL_OK
+    run.close()
+
+
+def test_force_deposit_after_sort_rejected(mods):
+    """p.fp is written in the particle order of a gather_push and a sort does
+    not move it: a deposit of F between a sort and the next gather_push is
+    refused on the host; after a gather_push it deposits what the fused step
+    deposits."""
+    oracle, driver, inputs, B = mods
+    say("[variants] force deposit from p.fp after a sort is refused")
+    wl = inputs.turbulent_box(n=16, npart=8 * 16 ** 3 - 5, steps=1)
+    run = driver.Run(wl, prec=B.PL_F64, algo=B.PL_ALGO_TILED, fp=True)
+    run.sort()
+    run.step()
+    assert run.sync() == B.PL_OK
+    run.items[0].m.eng = None                 # a deposit-only call has no energy channel
+    assert B.pl_part_deposit(run.ctx, run.items, B.PL_ZERO_FIRST, check=False) == B.PL_OK
+    run.sort()
+    assert B.pl_part_deposit(run.ctx, run.items, B.PL_ZERO_FIRST, check=False) == B.PL_EINVAL
+    run.step(flags=0)                         # push only: rewrites p.fp in the current order
+    assert B.pl_part_deposit(run.ctx, run.items, B.PL_ZERO_FIRST, check=False) == B.PL_OK
+    assert run.sync() == B.PL_OK
+    # the second push moved the particles again: compare with a fused step from the same state
+    ref = driver.Run(wl, prec=B.PL_F64, algo=B.PL_ALGO_TILED)
+    ref.sort()
+    ref.step(flags=0)
+    ref.sort()
+    ref.step()
+    assert ref.sync() == B.PL_OK
+    got = run.moments(0)
+    want = ref.moments(0)
+    for k in ("rho", "J", "F"):
+        g, w = np.asarray(got[k]), np.asarray(want[k])
+        assert np.abs(g - w).max() <= 1e-12 * np.abs(w).max(), k
+    run.close()
+    ref.close()

@@ -419,6 +419,29 @@ def test_paper_advection_rk3(orc):
         assert 3.5 < a / b < 9.0, e3
 
 
+def test_rk_time_order_cellular_flow(orc):
+    """Sec. 4.1.1: second order for the two-stage and third order for the
+    three-stage option.  On a fixed fine field grid only dt is refined, and
+    the error at t = 3 is taken against the exact trajectory of the
+    interpolated field (tests/_flows.py): halving dt divides it by about 4
+    and 8."""
+    from tests import _flows
+    vg = _flows.field()
+    ref = _flows.reference(orc, vg)
+    n = (_flows.N, _flows.N, 1)
+    dx = (_flows.DX,) * 3
+    for rk, lo, hi in ((2, 1.8, 2.2), (3, 2.8, 3.3)):
+        errs = []
+        for nsteps in (120, 240, 480, 960):
+            x = np.array([[_flows.X0[0]], [_flows.X0[1]], [0.0]])
+            u = np.zeros((3, 1))
+            for _ in range(nsteps):
+                orc.step(2, n, 2, (2, 0.0, 1.0, 0.0, rk), x, u, None, {"vg": vg}, _flows.T / nsteps, dx=dx)
+            errs.append(_flows.distance(x[:, 0], ref))
+        slopes = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+        assert all(lo < s < hi for s in slopes[1:]), (rk, errs, slopes)
+
+
 # ---------------------------------------------------------------- conservation
 
 def test_charge_and_momentum_conservation(orc):

@@ -154,11 +154,8 @@ def test_turbulent_f32_error_table(mods):
         say(f"  {k:4s} max {mx:.3e} rms {rms:.3e}")
     for k, (mx, rms, rel) in merr.items():
         say(f"  {k:4s} max/A_c {mx:.3e} rms/A_c {rms:.3e} max/max|M| {rel:.3e}")
-    for a in range(3):
-        assert table[f"x{a}"][0] <= 2e-5 and table[f"x{a}"][1] <= 2e-6
-        assert table[f"u{a}"][0] <= 2e-5 and table[f"u{a}"][1] <= 2e-6
-    for k, (mx, rms, rel) in merr.items():
-        assert mx <= 2e-5 and rms <= 2e-6, k
+    bad = _cmp.check_fp32_table(table, merr)
+    assert not bad, bad
     run.close()
 
 

@@ -224,11 +224,8 @@ def test_runs_f32_error_table(mods):
         say(f"  {k:4s} max {mx:.3e} rms {rms:.3e}")
     for k, (mx, rms, rel) in merr.items():
         say(f"  {k:4s} max/A_c {mx:.3e} rms/A_c {rms:.3e} max/max|M| {rel:.3e}")
-    for a in range(3):
-        assert table[f"x{a}"][0] <= 2e-5 and table[f"x{a}"][1] <= 2e-6
-        assert table[f"u{a}"][0] <= 2e-5 and table[f"u{a}"][1] <= 2e-6
-    for k, (mx, rms, rel) in merr.items():
-        assert mx <= 2e-5 and rms <= 2e-6, k
+    bad = _cmp.check_fp32_table(table, merr)
+    assert not bad, bad
     run.close()
 
 
@@ -284,7 +281,8 @@ def test_runs_drift_fp64_vs_oracle(mods):
     run, st = _run_gpu(driver, wl, wl.steps, True, prec=B.PL_F64, algo=B.PL_ALGO_RUNS, tile=(4, 4, 4))
     assert st == B.PL_OK
     _assert_runs_kernel(run, B)
-    _check_item(run, 0, ores[0], wl, X_TOL, 1e-11, M_TOL)
+    ex, eu, _ = _check_item(run, 0, ores[0], wl, X_TOL, U_TOL, M_TOL)
+    say(f"  max |dx| {ex:.3e} cells, max |du|/max(|u|, sigma) {eu:.3e}")
     run.close()
 
 

@@ -7,7 +7,10 @@ oracle.
   flow v = 2 + sin(pi x) on [-1, 1], 32 to 128 cells; the float64 GPU
   positions equal the oracle's, so their error against Eq. 10 follows the
   oracle's (second order for both schemes, the three-stage error at least
-  two times smaller; the TSC sampling error is O(dx^2)).
+  two times smaller; the TSC sampling error is O(dx^2));
+* the time orders themselves (Sec. 4.1.1: n^-2 and n^-3): a cellular flow on
+  a fixed fine grid with only dt refined, against the exact trajectory of
+  the interpolated field.
 """
 
 import math
@@ -110,3 +113,37 @@ def test_paper_advection_gpu(mods):
             assert a / b > 3.0, errs[rk]
     for a, b in zip(errs[3], errs[2]):
         assert a < 0.5 * b, errs
+
+
+def test_rk_time_order_gpu(mods):
+    """Sec. 4.1.1's orders on the GPU path: tracers in the steady cellular
+    flow of tests/_flows.py on a fixed 256^2 field grid, dt refined from
+    T/120 to T/960 (float64 plain kernel).  Every GPU end position equals the
+    oracle's, and against the exact trajectory of the interpolated field the
+    error falls by about 4 (two stages) and 8 (three stages) per halving."""
+    oracle, driver, inputs, B = mods
+    from tests import _flows
+    vg = _flows.field()
+    ref = _flows.reference(oracle, vg)
+    n = (_flows.N, _flows.N, 1)
+    for rk, lo, hi in ((2, 1.8, 2.2), (3, 2.8, 3.3)):
+        errs = []
+        for nsteps in (120, 240, 480, 960):
+            say(f"[tracer] cellular flow 256^2, {rk} stages, {nsteps} steps, float64 plain")
+            x = np.array([[_flows.X0[0]], [_flows.X0[1]], [0.0]])
+            wl = inputs.Workload(name="cellular flow",
+                                 boxes=[inputs.Box(2, n, {"vg": vg}, dx=(_flows.DX,) * 3)],
+                                 species=[inputs.Species("tracer", rk_stages=rk)],
+                                 items=[inputs.Item(0, 0, inputs.make_particles(x, np.zeros((3, 1))))],
+                                 dt=_flows.T / nsteps, steps=nsteps)
+            ores = oracle.run_workload(wl, abs_sums=False)
+            run, st = _run_gpu(driver, wl, nsteps, False, prec=B.PL_F64, algo=B.PL_ALGO_PLAIN)
+            # several cells per step at the coarsest dt: reported, still advanced
+            assert st in (B.PL_OK, B.PL_ECFL)
+            gx, gu, gid, _ = run.state(0)
+            assert _flows.distance(gx[:, 0], ores[0]["x"][:, 0]) < 1e-12
+            errs.append(_flows.distance(gx[:, 0], ref))
+            run.close()
+        slopes = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+        say(f"  {rk} stages: errors {errs}, slopes {slopes}")
+        assert all(lo < s < hi for s in slopes[1:]), (rk, errs, slopes)
