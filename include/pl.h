@@ -72,6 +72,7 @@ typedef int pl_status;
                                 context of another algorithm, or its count changed since the sort.
                                 That item's particles were left untouched and nothing was
                                 deposited for them */
+#define PL_ENOSPACE      8   /* pl_sort_noalloc: an item holds more than PL_NOALLOC_MAX_NP particles */
 
 /* Storage / arithmetic form of the particles. */
 #define PL_F64         0   /* float64 absolute grid coordinates and velocities */
@@ -295,6 +296,28 @@ pl_status pl_part_deposit(pl_ctx *ctx, const pl_item *items, int nitems, uint32_
  * in table order from tile_start[t]) and the entries point there.
  */
 pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems);
+
+/*
+ * pl_sort_noalloc: pl_part_sort for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  It needs no context: d is validated as by
+ * pl_part_init (ndim, prec, algo, key_mode, boxes with their tiles given,
+ * species, max_items, max_np; block and tune_cache are ignored) and the work
+ * is queued on d->stream.  The result is exactly that of pl_part_sort with a
+ * context made from d: same permutation, tile offsets, run table and flip of
+ * items[i].p.cur.  The sort's own scratch (keys, indices, digit histograms)
+ * is a fixed array inside the library, about 17 MB, which every GPU the
+ * library runs on holds until the process ends; nothing is allocated, and
+ * the array is set up on the first call on each device.
+ * Limits and errors: an item with more than PL_NOALLOC_MAX_NP particles
+ * returns PL_ENOSPACE, PL_KEY_TILE_RANK (per-cell scratch) and devices
+ * numbered 64 and above return PL_EUNSUPPORTED, a box without a tile
+ * returns PL_EINVAL; all of them before any device work.  All calls on one
+ * GPU share the array: calls that overlap on one GPU (several streams or
+ * threads) race; calls queued on one stream are ordered and safe.
+ */
+#define PL_NOALLOC_MAX_NP (1 << 20)
+pl_status pl_sort_noalloc(const pl_init_desc *d, pl_item *items, int nitems);
 
 /*
  * pl_part_pack: write item->p's current set from float64 device arrays

@@ -13,7 +13,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpl.so")
 
-PL_OK, PL_EINVAL, PL_ENOMEM, PL_EHIP, PL_EUNSUPPORTED, PL_ECFL, PL_ENONFINITE, PL_ENOTSORTED = range(8)
+PL_OK, PL_EINVAL, PL_ENOMEM, PL_EHIP, PL_EUNSUPPORTED, PL_ECFL, PL_ENONFINITE, PL_ENOTSORTED, PL_ENOSPACE = range(9)
+PL_NOALLOC_MAX_NP = 1 << 20
 PL_NSTATS = 8
 PL_F64, PL_F32_OFFSET = 0, 1
 PL_CIC, PL_TSC = 1, 2
@@ -30,7 +31,7 @@ PL_FUSE_DEPOSIT, PL_ZERO_FIRST, PL_GRAPH, PL_SUMS = 1, 2, 4, 8
 
 EXPORTS = ["pl_part_init", "pl_part_gather_push", "pl_part_deposit", "pl_part_sort", "pl_part_pack",
            "pl_part_unpack", "pl_part_sums", "pl_part_sync", "pl_part_set_stream", "pl_part_stats",
-           "pl_part_finalize", "pl_status_string"]
+           "pl_part_finalize", "pl_status_string", "pl_sort_noalloc"]
 
 _vp = C.c_void_p
 
@@ -92,6 +93,7 @@ def lib():
         L.pl_part_gather_push.argtypes = [_vp, P(pl_item), C.c_int, C.c_double, C.c_uint32]
         L.pl_part_deposit.argtypes = [_vp, P(pl_item), C.c_int, C.c_uint32]
         L.pl_part_sort.argtypes = [_vp, P(pl_item), C.c_int]
+        L.pl_sort_noalloc.argtypes = [P(pl_init_desc), P(pl_item), C.c_int]
         L.pl_part_pack.argtypes = [_vp, P(pl_item), P(_vp), P(_vp)]
         L.pl_part_unpack.argtypes = [_vp, P(pl_item), P(_vp), P(_vp)]
         L.pl_part_sums.argtypes = [_vp, P(pl_item), C.c_int, P(C.c_double)]
@@ -147,6 +149,13 @@ def pl_part_sort(ctx, items, check=True):
     arr, n = _items_arg(items)
     st = lib().pl_part_sort(ctx, arr, n)
     return _check(st, "pl_part_sort") if check else st
+
+
+def pl_sort_noalloc(desc, items, check=True):
+    """pl_part_sort without a context, its scratch in the library's fixed array."""
+    arr, n = _items_arg(items)
+    st = lib().pl_sort_noalloc(C.byref(desc), arr, n)
+    return _check(st, "pl_sort_noalloc") if check else st
 
 
 def _ptr3(ptrs):

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "pl_device.h"
 
@@ -577,6 +578,63 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
         c->stats[0] += 2;
     }
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of pl_sort_noalloc: keys and indices (two buffers each) for
+// PL_NOALLOC_MAX_NP particles and the digit histograms and their scan.  Every
+// GPU the library runs on holds one copy until the process ends; all calls on
+// a device share it (calls that overlap on one device race).
+// ---------------------------------------------------------------------------
+
+constexpr int64_t kNaNp = PL_NOALLOC_MAX_NP;
+constexpr int64_t kNaHist = 256 * ((kNaNp + kPerBlock - 1) / kPerBlock) + 1024;
+constexpr size_t kNaBytes = (size_t)(4 * kNaNp + 2 * kNaHist) * sizeof(uint32_t);
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+constexpr int kNaDevices = 64;
+static std::mutex na_mu;
+static void *na_ptr[kNaDevices];       // device address of `scratch` on each device
+static int na_cu[kNaDevices];
+
+hipError_t launch_sort_noalloc(Ctx *c, const SortArgs &a)
+{
+    if (a.np > kNaNp) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNaDevices) return hipErrorInvalidDevice;
+    void *base = nullptr;
+    int cu = 0;
+    {
+        std::lock_guard<std::mutex> lock(na_mu);
+        if (!na_ptr[dev]) {
+            // once per device, with that device current: the array's device
+            // address (the symbol itself is a host-side stand-in)
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            int n = 0;
+            e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e != hipSuccess) return e;
+            na_cu[dev] = n > 0 ? n : 1;
+            na_ptr[dev] = p;
+        }
+        base = na_ptr[dev];
+        cu = na_cu[dev];
+    }
+    uint32_t *w = static_cast<uint32_t *>(base);
+    c->num_cu = cu;
+    c->keys[0] = w;
+    c->keys[1] = w + kNaNp;
+    c->idx[0] = w + 2 * kNaNp;
+    c->idx[1] = w + 3 * kNaNp;
+    c->hist = w + 4 * kNaNp;
+    c->hist_scan = w + 4 * kNaNp + kNaHist;
+    c->hist_cap = kNaHist;
+    c->cell_start = nullptr;           // PL_KEY_TILE_RANK is refused before this point
+    return launch_sort(c, a);
 }
 
 }  // namespace pl

@@ -142,8 +142,8 @@ pl_status make_desc(const Ctx *c, const pl_item &it, double dt, Mode mode, bool 
 {
     const pl_init_desc &d = c->d;
     if (it.box < 0 || it.box >= d.nboxes || it.species < 0 || it.species >= d.nspecies) return PL_EINVAL;
-    const pl_box_desc &bx = c->boxes[it.box];
-    const pl_species_desc &sp = c->species[it.species];
+    const pl_box_desc &bx = d.boxes[it.box];
+    const pl_species_desc &sp = d.species[it.species];
     const pl_particles &p = it.p;
     if (p.n < 0 || p.n > c->max_np) return PL_EINVAL;
     if (p.cur != 0 && p.cur != 1) return PL_EINVAL;
@@ -508,22 +508,23 @@ pl_status pl_part_deposit(pl_ctx *ctx, const pl_item *items, int nitems, uint32_
     return run_call(c, items, nitems, 0.0, flags, MODE_DEPOSIT);
 }
 
-pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems)
+}  // extern "C"
+
+namespace {
+
+// Validate one item of a sort call and describe it to the sort launcher.
+pl_status sort_args(const Ctx *c, const pl_item &it, SortArgs &a)
 {
-    Ctx *c = reinterpret_cast<Ctx *>(ctx);
-    if (!c || !items || nitems < 1 || nitems > c->d.max_items) return PL_EINVAL;
     const bool f64 = c->d.prec == PL_F64;
     const size_t es = f64 ? 8 : 4;
-    std::vector<SortArgs> args(nitems);
-    for (int i = 0; i < nitems; ++i) {
-        const pl_item &it = items[i];
+    {
         ItemDesc D;
         pl_status st = make_desc(c, it, 1.0, MODE_QUERY, false, D);
         if (st != PL_OK) return st;
         const pl_particles &p = it.p;
         if (!p.tile_start || !aligned(p.tile_start, 4)) return PL_EINVAL;
+        if (c->d.algo == PL_ALGO_RUNS && !p.runs) return PL_EINVAL;
         const int cur = p.cur, nxt = 1 - p.cur;
-        SortArgs &a = args[i];
         memset(&a, 0, sizeof(a));
         a.prec = c->d.prec;
         a.ndim = c->d.ndim;
@@ -556,6 +557,22 @@ pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems)
         if (p.id[cur] && !aligned(p.id[cur], 8)) ok = false;
         if (!ok) return PL_EINVAL;
     }
+    return PL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems)
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || !items || nitems < 1 || nitems > c->d.max_items) return PL_EINVAL;
+    std::vector<SortArgs> args(nitems);
+    for (int i = 0; i < nitems; ++i) {
+        pl_status st = sort_args(c, items[i], args[i]);
+        if (st != PL_OK) return st;
+    }
     for (int i = 0; i < nitems; ++i) {
         if (launch_sort(c, args[i]) != hipSuccess) return PL_EHIP;
         items[i].p.cur = 1 - items[i].p.cur;
@@ -565,6 +582,39 @@ pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems)
             // bounded: the oldest entry goes first
             if (c->fp_stale.size() >= c->fp_stale.capacity()) c->fp_stale.erase(c->fp_stale.begin());
             c->fp_stale.push_back(fp);
+        }
+    }
+    return PL_OK;
+}
+
+pl_status pl_sort_noalloc(const pl_init_desc *d, pl_item *items, int nitems)
+{
+    pl_status st = validate_desc(d);
+    if (st != PL_OK) return st;
+    if (!items || nitems < 1 || nitems > d->max_items) return PL_EINVAL;
+    if (d->key_mode == PL_KEY_TILE_RANK) return PL_EUNSUPPORTED;       // needs per-cell scratch
+    for (int b = 0; b < d->nboxes; ++b)
+        if (d->boxes[b].tile[0] == 0) return PL_EINVAL;                 // no tune cache here: tiles are given
+    for (int i = 0; i < nitems; ++i)
+        if (items[i].p.n > PL_NOALLOC_MAX_NP) return PL_ENOSPACE;
+    // a context on the stack that only carries the description: nothing is
+    // allocated, the sort scratch is the library's fixed device array
+    Ctx c;
+    c.d = *d;
+    c.max_np = d->max_np;
+    c.stream = (hipStream_t)d->stream;
+    SortArgs a[8];
+    for (int i0 = 0; i0 < nitems; i0 += 8) {
+        const int i1 = std::min(nitems, i0 + 8);
+        for (int i = i0; i < i1; ++i) {
+            st = sort_args(&c, items[i], a[i - i0]);
+            if (st != PL_OK) return st;
+        }
+        for (int i = i0; i < i1; ++i) {
+            hipError_t e = launch_sort_noalloc(&c, a[i - i0]);
+            if (e == hipErrorInvalidDevice) return PL_EUNSUPPORTED;
+            if (e != hipSuccess) return PL_EHIP;
+            items[i].p.cur = 1 - items[i].p.cur;
         }
     }
     return PL_OK;
@@ -682,6 +732,7 @@ const char *pl_status_string(pl_status s)
     case PL_EUNSUPPORTED: return "unsupported request";
     case PL_ECFL: return "a particle moved a full cell or more in one step";
     case PL_ENONFINITE: return "non-finite or out-of-range particle coordinate";
+    case PL_ENOSPACE: return "the request exceeds the fixed scratch of pl_sort_noalloc";
     case PL_ENOTSORTED: return "an item's tile offsets or run table do not cover its particles (sort it first)";
     default: return "unknown status";
     }

@@ -168,5 +168,8 @@ struct SortArgs {
     int32_t *runs;                   // nullable: run table to build (PL_ALGO_RUNS)
 };
 hipError_t launch_sort(Ctx *c, const SortArgs &a);
+// The same sort with its scratch in the library's fixed device array (set up
+// on the first call on each device); c supplies the stream only.
+hipError_t launch_sort_noalloc(Ctx *c, const SortArgs &a);
 
 }  // namespace pl

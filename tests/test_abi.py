@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_status_strings(lib):
-    for s in range(8):
+    for s in range(9):
         assert B.pl_status_string(s) not in ("", "unknown status")
     assert "sort" in B.pl_status_string(B.PL_ENOTSORTED)
     assert B.pl_status_string(99) == "unknown status"
