@@ -89,8 +89,22 @@ def lib():
         L.orc_num_threads.argtypes = []
         L.orc_stable_sort_perm.restype = None
         L.orc_stable_sort_perm.argtypes = [C.c_long, C.POINTER(C.c_uint32), C.POINTER(C.c_long)]
+        L.orc_spectra_step.restype = None
+        L.orc_spectra_step.argtypes = [C.POINTER(_Box), C.c_int, C.c_double, C.c_long, _P * 3,
+                                       C.POINTER(_Fields), _P, C.c_int, _P, _P, C.c_double,
+                                       C.POINTER(_SpectraPar)]
+        L.orc_outside.restype = C.c_int
+        L.orc_outside.argtypes = [C.POINTER(_Box), C.c_int * 3, C.c_int, _P]
+        L.orc_compact.restype = C.c_long
+        L.orc_compact.argtypes = [C.c_long, C.POINTER(C.c_ubyte), C.c_int, C.POINTER(C.c_void_p),
+                                  C.POINTER(C.c_size_t), C.POINTER(C.c_long), C.POINTER(C.c_long),
+                                  C.POINTER(C.c_long)]
         _LIB = L
     return _LIB
+
+
+class _SpectraPar(C.Structure):
+    _fields_ = [("cr", C.c_double), ("u_rad", C.c_double), ("ub", C.c_double)]
 
 
 def _dp(a):
@@ -281,3 +295,62 @@ def run_workload(wl, steps=None, c=1.0, abs_sums=True, fp=False):
                          wl.dt, c=c, dx=box.dx, moments=mom, abs_moments=am, fp=fpa)
         out.append({"x": x, "u": u, "w": w, "moments": mom, "abs": am, "violations": viol, "fp": fpa})
     return out
+
+
+def spectra_step(ndim, n, shape, x, fields, divu, eng, chi, dt, cr, u_rad=0.0, ub=0.5, c=1.0,
+                 dx=(1.0, 1.0, 1.0)):
+    """One step of the particles' energy distributions in place.
+
+    ``x`` (3, np) grid positions; ``fields`` maps "B" and "vg" to
+    (3, nz, ny, nx) arrays; ``divu`` (nz, ny, nx) the four-divergence of the
+    fluid velocity; ``eng``, ``chi`` (np, nb) particle-major float64.
+    Loss coefficient c_r = cr (ub |B|^2 + u_rad)."""
+    b = _box(ndim, n, dx)
+    npart = x.shape[1]
+    assert eng.shape == chi.shape and eng.shape[0] == npart
+    assert eng.flags.c_contiguous and chi.flags.c_contiguous
+    xs = (_P * 3)(*[_dp(x[d]) for d in range(3)])
+    f = _Fields()
+    keep = []
+    for name in ("B", "vg"):
+        for d in range(3):
+            a = np.ascontiguousarray(fields[name][d], dtype=np.float64)
+            keep.append(a)
+            getattr(f, name)[d] = _dp(a)
+    dv = np.ascontiguousarray(divu, dtype=np.float64)
+    par = _SpectraPar(float(cr), float(u_rad), float(ub))
+    lib().orc_spectra_step(C.byref(b), shape, float(c), npart, xs, C.byref(f), _dp(dv), eng.shape[1],
+                           _dp(eng), _dp(chi), float(dt), C.byref(par))
+
+
+def outside(ndim, n, open_dims, ghost, x):
+    """Per particle: 1 if grid position x[:, p] lies outside the active cells of
+    an open dimension."""
+    b = _box(ndim, n)
+    od = (C.c_int * 3)(*[int(v) for v in open_dims])
+    out = np.zeros(x.shape[1], dtype=np.uint8)
+    xx = np.zeros(3)
+    for p in range(x.shape[1]):
+        xx[:] = x[:, p]
+        out[p] = lib().orc_outside(C.byref(b), od, int(ghost), _dp(xx))
+    return out
+
+
+def compact(flag, arrays):
+    """Holes-and-fillers compaction (in place) of the 1-D numpy arrays in
+    ``arrays`` (the same length, any dtypes); returns (new count, holes,
+    fillers) with the copied pairs in order."""
+    flag = np.ascontiguousarray(flag, dtype=np.uint8)
+    npart = flag.shape[0]
+    for a in arrays:
+        assert a.shape[0] == npart and a.flags.c_contiguous
+    ptrs = (C.c_void_p * max(1, len(arrays)))(*[a.ctypes.data for a in arrays])
+    esz = (C.c_size_t * max(1, len(arrays)))(*[a.itemsize * (a.size // max(npart, 1)) for a in arrays])
+    holes = np.zeros(max(npart, 1), dtype=np.int64)
+    fills = np.zeros(max(npart, 1), dtype=np.int64)
+    nc = C.c_long()
+    keep = lib().orc_compact(npart, flag.ctypes.data_as(C.POINTER(C.c_ubyte)), len(arrays), ptrs, esz,
+                             holes.ctypes.data_as(C.POINTER(C.c_long)), fills.ctypes.data_as(C.POINTER(C.c_long)),
+                             C.byref(nc))
+    return int(keep), holes[: nc.value].copy(), fills[: nc.value].copy()
+

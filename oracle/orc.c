@@ -393,3 +393,120 @@ void orc_stable_sort_perm(long np, const uint32_t *key, long *perm)
     for (long p = 0; p < np; ++p) perm[p] = t[p].idx;
     free(t);
 }
+
+/* ------------------------------------------------------------------ */
+/* Lagrangian spectral update (Sec. 2)                                 */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Each particle carries its energy distribution as nb points (eps_i, chi_i),
+ * chi = N / n the number density per unit energy relative to the fluid's
+ * (Eq. chi).  Away from shocks chi obeys Eq. cr_chi: it is carried in energy
+ * with the rate
+ *     d eps / d tau = -(eps / 3) div_mu u^mu - c_r eps^2          (Eq. cr_N)
+ * (adiabatic term, and synchrotron plus inverse-Compton losses with
+ * c_r = cr (U_B + U_rad), Eq. rad_losses; U_B = ub |B|^2), while
+ * d chi / d tau = -chi d(d eps/d tau)/d eps along each characteristic.
+ * Proper and laboratory time: d tau = dt / gamma_g (Sec. 2).
+ *
+ * With the fluid quantities frozen over the step (a = div u / 3, b = c_r)
+ * both are solved exactly:
+ *     eps(tau) = a eps0 e^{-a tau} / (a + b eps0 (1 - e^{-a tau})),
+ * i.e. eps = eps0 E / den with E = e^{-a tau}, den = 1 + b eps0 phi,
+ * phi = (1 - e^{-a tau}) / a (-> tau as a -> 0), and since
+ * d eps / d eps0 = E / den^2 and chi d eps is conserved on a characteristic,
+ *     chi(tau) = chi0 den^2 / E.
+ * Each point of the spectrum moves on its own characteristic (a Lagrangian
+ * grid in energy), so the number between two neighbouring points is
+ * conserved.  The fluid quantities are sampled at the particle position with
+ * the same CIC/TSC weights as orc_gather.  Arrays are particle-major:
+ * eng[p * nb + i], chi[p * nb + i].
+ */
+void orc_spectra_step(const orc_box *b, int shape, double c, long np, double *x[3], const orc_fields *f,
+                      const double *divu, int nb, double *eng, double *chi, double dt, const orc_spectra_par *par)
+{
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < np; ++p) {
+        double xp[3] = {x[0][p], x[1][p], b->ndim == 3 ? x[2][p] : 0.0};
+        double Bp[3], vp[3];
+        for (int d = 0; d < 3; ++d) {
+            Bp[d] = orc_gather(b, shape, f->B[d], xp);
+            vp[d] = orc_gather(b, shape, f->vg[d], xp);
+        }
+        double dv = orc_gather(b, shape, divu, xp);
+        double gamma_g = 1.0 / sqrt(1.0 - dot(vp, vp) / (c * c));
+        double dtau = dt / gamma_g;
+        double a = dv / 3.0;
+        double bb = par->cr * (par->ub * dot(Bp, Bp) + par->u_rad);
+        double E = exp(-a * dtau);
+        double phi = a != 0.0 ? -expm1(-a * dtau) / a : dtau;
+        for (int i = 0; i < nb; ++i) {
+            double eps0 = eng[p * nb + i];
+            double den = 1.0 + bb * eps0 * phi;
+            eng[p * nb + i] = eps0 * E / den;
+            chi[p * nb + i] = chi[p * nb + i] * den * den / E;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Open boundaries: deletion and compaction (Sec. 3.2)                 */
+/* ------------------------------------------------------------------ */
+
+/*
+ * A particle leaves through an open dimension d when its cell lies outside
+ * the active cells [ghost, n_d - ghost): the grid keeps `ghost` layers of
+ * boundary cells on each open side, so the stencils of the particles that
+ * were active at the start of a step stay inside the grid arrays.
+ */
+int orc_outside(const orc_box *b, const int open[3], int ghost, const double x[3])
+{
+    for (int d = 0; d < b->ndim; ++d) {
+        if (!open[d]) continue;
+        double cell = floor(x[d]);
+        if (cell < (double)ghost || cell >= (double)(b->n[d] - ghost)) return 1;
+    }
+    return 0;
+}
+
+/*
+ * The compaction of Sec. 3.2, step by step:
+ *   1. count the ndel flagged particles (the holes to be);
+ *   2. save the indices of the flagged particles in a temporary array;
+ *   3. collect the fillers: unflagged particles stored at i >= np - ndel;
+ *   4. copy every array of the k-th filler into the k-th saved hole below
+ *      np - ndel (both lists in increasing index order);
+ *   5. shrink to np - ndel.
+ * Arrays: narr arrays of np elements of esz[k] bytes each, moved together.
+ * Returns the new count; hole_out / filler_out (nullable, np entries) receive
+ * the pairs actually copied, and *ncopied their number.
+ */
+long orc_compact(long np, const unsigned char *flag, int narr, void *const arr[], const size_t esz[],
+                 long *hole_out, long *filler_out, long *ncopied)
+{
+    long ndel = 0;
+    for (long p = 0; p < np; ++p) ndel += flag[p] != 0;                 /* 1 */
+    long *tmp = (long *)malloc(sizeof(long) * (size_t)(np > 0 ? np : 1));
+    long nsaved = 0;
+    for (long p = 0; p < np; ++p)                                       /* 2 */
+        if (flag[p]) tmp[nsaved++] = p;
+    long keep = np - ndel;
+    long *fill = (long *)malloc(sizeof(long) * (size_t)(ndel > 0 ? ndel : 1));
+    long nfill = 0;
+    if (nsaved > 0)                                                     /* 3 */
+        for (long p = keep; p < np; ++p)
+            if (!flag[p]) fill[nfill++] = p;
+    long k = 0;
+    for (long h = 0; h < nsaved && tmp[h] < keep; ++h, ++k) {           /* 4 */
+        for (int a = 0; a < narr; ++a) {
+            unsigned char *base = (unsigned char *)arr[a];
+            memcpy(base + (size_t)tmp[h] * esz[a], base + (size_t)fill[k] * esz[a], esz[a]);
+        }
+        if (hole_out) hole_out[k] = tmp[h];
+        if (filler_out) filler_out[k] = fill[k];
+    }
+    if (ncopied) *ncopied = k;
+    free(fill);
+    free(tmp);
+    return keep;                                                        /* 5 */
+}

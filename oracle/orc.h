@@ -1,7 +1,9 @@
 /*
  * Reference CPU implementation ("oracle") of the per-step particle update:
  * gather of grid fields to particles with CIC/TSC weights, Boris / drag /
- * tracer advance, deposit of particle moments, and the stable cell-tile sort.
+ * tracer advance, deposit of particle moments, the stable cell-tile sort, the
+ * Lagrangian spectral update, and deletion with compaction at open
+ * boundaries.
  *
  * TEST INFRASTRUCTURE ONLY.  The test-suite, the smoke check and the
  * benchmark's CPU-baseline leg call it; the GPU library never includes,
@@ -15,6 +17,7 @@
 #ifndef ORC_H
 #define ORC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -87,6 +90,24 @@ int orc_num_threads(void);
 
 /* Stable sort: perm[r] = index of the particle that lands at rank r. */
 void orc_stable_sort_perm(long np, const uint32_t *key, long *perm);
+
+/* Parameters of the spectral update: the loss coefficient is
+ * c_r = cr * (ub * |B|^2 + u_rad) (Eq. rad_losses, U_B = ub |B|^2). */
+typedef struct { double cr, u_rad, ub; } orc_spectra_par;
+
+/* One step dt of the energy distributions of np particles (nb points each,
+ * particle-major eng[p*nb+i], chi[p*nb+i]), fluid quantities B, vg and divu
+ * (the four-divergence of the fluid velocity) sampled at positions x. */
+void orc_spectra_step(const orc_box *b, int shape, double c, long np, double *x[3], const orc_fields *f,
+                      const double *divu, int nb, double *eng, double *chi, double dt, const orc_spectra_par *par);
+
+/* 1 when grid position x lies outside the active cells [ghost, n - ghost) of
+ * an open dimension (open[d] != 0), else 0. */
+int orc_outside(const orc_box *b, const int open[3], int ghost, const double x[3]);
+
+/* Holes-and-fillers compaction of Sec. 3.2 (see orc.c); returns the new count. */
+long orc_compact(long np, const unsigned char *flag, int narr, void *const arr[], const size_t esz[],
+                 long *hole_out, long *filler_out, long *ncopied);
 
 #ifdef __cplusplus
 }

@@ -274,6 +274,55 @@ def batched(n_main=192, n_cr=40_000_000, n_dust=8_000_000, n_tracer=1_000_000,
                     notes={"small_counts": counts.tolist()})
 
 
+def powerlaw_spectrum(nb=128, emin=1e2, emax=1e4, p=9.0, n0=1e-6):
+    """The initial particle spectrum of the paper's shock test (Sec. 4.2):
+    nb energies log-spaced from emin to emax and the power law
+    chi = n0 (1 - p) / (emax^(1-p) - emin^(1-p)) * eps^(-p), whose integral
+    over [emin, emax] is n0.  Returns (eng, chi), each of shape (nb,)."""
+    eng = np.geomspace(emin, emax, nb)
+    norm = n0 * (1.0 - p) / (emax ** (1.0 - p) - emin ** (1.0 - p))
+    return eng, norm * eng ** (-p)
+
+
+def scalar_field(n, seed, rms, kmax_frac=0.25, slope=-11.0 / 6.0):
+    """Random scalar field on an n^3 periodic grid with the turbulent recipe's
+    mode amplitudes (no projection), rescaled to the given rms.  Stands in for
+    the fluid's four-velocity divergence (compressions and expansions)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = n
+    kx = np.fft.rfftfreq(nx, 1.0 / nx)
+    ky = np.fft.fftfreq(ny, 1.0 / ny)
+    kz = np.fft.fftfreq(nz, 1.0 / nz)
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    kmag = np.sqrt(KX * KX + KY * KY + KZ * KZ)
+    live = (kmag >= 1.0) & (kmag <= kmax_frac * min(nx, ny, nz))
+    amp = np.zeros_like(kmag)
+    amp[live] = kmag[live] ** slope
+    coef = (rng.standard_normal(kmag.shape) + 1j * rng.standard_normal(kmag.shape)) * (amp / math.sqrt(2.0))
+    f = np.fft.irfftn(coef, s=(nz, ny, nx), axes=(0, 1, 2))
+    return f * (rms / math.sqrt(float(np.mean(f * f))))
+
+
+def spectra_box(n=160, ppc=4, nb=128, steps=10, k=5, divu_rms=0.1, dt=0.05):
+    """The paper's Lagrangian-particle workload shape (Sec. 4.2, Table 1): n^3
+    cells with ppc particles per cell (160^3 x 4 = 16 384 000 per GPU), each
+    carrying nb spectral points initialised to the power law of
+    powerlaw_spectrum; turbulent B and gas velocity, and a random
+    four-divergence field (rms divu_rms) for the adiabatic term.  The spectra
+    are returned as one (nb,) template (every particle starts with it)."""
+    nn = (n, n, n)
+    flds = turbulent_fields(nn, SEED_B + k, SEED_V + k)
+    flds["divu"] = scalar_field(nn, SEED_V + 100 + k, divu_rms)
+    rng = np.random.default_rng(SEED_P + k)
+    npart = ppc * n ** 3
+    x = uniform_positions(rng, npart, nn, 3)
+    box = Box(ndim=3, n=nn, fields=flds)
+    eng, chi = powerlaw_spectrum(nb)
+    return Workload(name=f"spectra {n}^3, {npart} particles, {nb} bins", boxes=[box],
+                    species=[Species("tracer")], items=[Item(0, 0, make_particles(x, np.zeros((3, npart))))],
+                    dt=dt, steps=steps, notes={"eng0": eng, "chi0": chi})
+
+
 def scaled(kind, scale):
     """Smaller versions of the workloads with the same recipe (for tests).
 
