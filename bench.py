@@ -6,13 +6,21 @@ Maxwellian velocities (sigma = 0.05 c), TSC weights, dt = 0.05; every step
 gathers E and B, pushes (relativistic Boris) and deposits rho, J and F at the
 new positions.  The headline path is the float32 + cell-offset form with the
 run-based LDS kernel; its sort (particles in run order: tile, run inside the
-cell, cell) runs inside the timed loop at the tuned cadence.  The plain float64 path runs on the same inputs for the
-speedup, and the run-based float64 path and the tiled float32 path beside it.
+cell, cell) runs inside the timed loop at the tuned cadence.  The plain float64
+path runs on the same inputs for the speedup, and the run-based float64 path
+and the tiled float32 path beside it.
 
 Each timed step: zero the moment grids, then one fused gather/push/deposit
 launch (a replayed hipGraph) bracketed by HIP events on the library's stream;
 sorts are bracketed separately.  Prints ONE JSON line.  Inputs are generated
 on the host and are resident in HBM before the timed region starts.
+
+Beside the headline, in the same line: the clumped 256^3 box and the batched
+workload (each with its own roofline), the Lagrangian spectral update on the
+paper's particle workload (160^3 cells x 4 particles, 128 spectral points
+each), the open-boundary deletion and compaction pass, the float32 error
+table measured by the parity tests on the same kernel sources, and the
+float64 oracle timed on the host cores (all threads and one).
 """
 
 from __future__ import annotations
@@ -23,6 +31,8 @@ import os
 import statistics
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -45,6 +55,7 @@ def kernel_name(cfg, B):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_runs_f32_turbulent128_traffic.json")
 INSTR_FILE = os.path.join(ROOT, "profiles", "k_runs_f32_turbulent128_instructions.json")
+ERR_FILE = os.path.join(ROOT, "profiles", "f32_error_table_turbulent32.json")
 
 
 def log(msg):
@@ -111,9 +122,51 @@ def time_path(run, steps, warmup, reps, every, graph, torch, B):
             "kernel_ms": sum(kern) / len(kern), "sort_ms": (sum(sorts) / len(sorts)) if sorts else 0.0}
 
 
+def touched_cells(x, n):
+    """Distinct cells in the union of the particles' TSC stencils (3^3 around
+    each particle's cell, periodic), from float64 grid positions (3, np)."""
+    import numpy as np
+    nx, ny, nz = n
+    c = [np.floor(np.mod(x[d], n[d])).astype(np.int64) % n[d] for d in range(3)]
+    occ = np.zeros(nx * ny * nz, dtype=bool)
+    occ[c[0] + nx * (c[1] + ny * c[2])] = True
+    g = occ.reshape(nz, ny, nx)
+    for ax in (2, 1, 0):
+        g = g | np.roll(g, 1, axis=ax) | np.roll(g, -1, axis=ax)
+    return int(g.sum())
+
+
+# float32 form, bytes per particle read and written (cell 4, offsets 12, u 12, w 4 read; no w written)
+F32_PART = 32 + 28
+KIND_FIELDS = {"lorentz": 48, "dust": 24, "tracer": 24}     # E,B / gas velocity, float64
+KIND_MOMENTS = {"lorentz": 7, "dust": 4, "tracer": 0}       # channels deposited, float64
+
+
+def workload_bytes(wl, per_box_cells):
+    """Algorithmic bytes of one step of every item of a float32 workload and
+    of its charged items alone: each particle read and written once, each
+    touched cell's fields read once per box and kind of field, each touched
+    moment cell read-modify-written once per channel."""
+    total = charged = 0
+    fields_seen = set()
+    for it in wl.items:
+        kind = wl.species[it.species].kind
+        cells = per_box_cells[it.box]
+        fkey = (it.box, "EB" if kind == "lorentz" else "vg")
+        fbytes = 0 if fkey in fields_seen else KIND_FIELDS[kind] * cells
+        fields_seen.add(fkey)
+        b = F32_PART * it.particles.n + fbytes + 2 * 8 * KIND_MOMENTS[kind] * cells
+        total += b
+        if kind == "lorentz":
+            charged += F32_PART * it.particles.n + KIND_FIELDS[kind] * cells + 2 * 8 * 7 * cells
+    return total, charged
+
+
 def time_workload(wl, cfg, steps, every, torch, B, driver):
     """Whole-step time of a multi-item workload (all items in one call per
-    step: one persistent launch per species kind), sort every `every` steps."""
+    step: one persistent launch per species kind), sort every `every` steps,
+    and the charged-particle run kernel's time per launch (HIP events on the
+    library's stream, one call per kind)."""
     run = driver.Run(wl, **cfg)
     try:
         run.sort()
@@ -122,10 +175,26 @@ def time_workload(wl, cfg, steps, every, torch, B, driver):
         timed_loop(run, 2, every, True, torch, B)
         ms, kern, sorts = timed_loop(run, steps, every, True, torch, B)
         stats = B.pl_part_stats(run.ctx)
+        # the charged items alone, one call per step (their own launch)
+        ci = [i for i, it in enumerate(wl.items) if wl.species[it.species].kind == "lorentz"]
+        sub = (B.pl_item * len(ci))(*[run.items[i] for i in ci])
+        ev = lambda: torch.cuda.Event(enable_timing=True)
+        pairs = []
+        for _ in range(steps):
+            run.zero_moments()
+            a, b = ev(), ev()
+            a.record(run.stream)
+            run.step(flags=B.PL_FUSE_DEPOSIT | B.PL_GRAPH, items=sub)
+            b.record(run.stream)
+            pairs.append((a, b))
+        torch.cuda.synchronize()
+        if run.sync() != B.PL_OK:
+            raise RuntimeError("device reported an error")
+        charged_ms = sum(a.elapsed_time(b) for a, b in pairs) / len(pairs)
         return {"value": total * steps / (ms * 1e-3), "unit": "particle-updates/s", "particles": total,
                 "ms_per_step": ms / steps, "kernel_ms": sum(kern) / len(kern),
                 "sort_ms": (sum(sorts) / len(sorts)) if sorts else 0.0, "sort_every": every, "steps": steps,
-                "run_kernel_launches": stats[4], "tiled_fallback_groups": stats[5]}
+                "charged_kernel_ms": charged_ms, "run_kernel_launches": stats[4], "tiled_fallback_groups": stats[5]}
     finally:
         run.close()
 
@@ -134,55 +203,170 @@ def extra_workloads(head_cfg, torch, B, driver, inputs):
     """The clumped 256^3 box (2^26 particles, half in 32 Gaussian clumps, sort
     every 4 steps) and the batched workload (192^3 box with charged, dust and
     tracer species plus 16 independent 64^3 boxes), both in the float32 form
-    with the headline's kernel configuration, 20 steps each."""
+    with the headline's kernel configuration, 20 steps each, each with its
+    roofline: algorithmic bytes of the charged run kernel's launch over its
+    time, and of the whole step (sort amortised) over the step time."""
     out = {}
     cfg = {k: v for k, v in head_cfg.items() if k != "sort_every"}
-    t0 = time.perf_counter()
-    wl = inputs.clumped_box()
-    log(f"[bench] clumped 256^3 inputs in {time.perf_counter() - t0:.1f} s")
-    out["clumped_256"] = time_workload(wl, cfg, 20, 4, torch, B, driver)
-    log(f"[bench] clumped 256^3: {out['clumped_256']}")
-    del wl
-    torch.cuda.empty_cache()
-    t0 = time.perf_counter()
-    wl = inputs.batched()
-    log(f"[bench] batched inputs in {time.perf_counter() - t0:.1f} s")
-    bcfg = dict(cfg)
-    bcfg["channels"] = None
-    out["batched_192"] = time_workload(wl, bcfg, 20, head_cfg["sort_every"], torch, B, driver)
-    log(f"[bench] batched: {out['batched_192']}")
-    del wl
-    torch.cuda.empty_cache()
+    for name, make, every, chans in (("clumped_256", inputs.clumped_box, 4, cfg.get("channels")),
+                                     ("batched_192", inputs.batched, head_cfg["sort_every"], None)):
+        t0 = time.perf_counter()
+        wl = make()
+        cells = [touched_cells(it.particles.x, wl.boxes[it.box].n) for it in wl.items]
+        per_box = {}
+        for it, c in zip(wl.items, cells):
+            per_box[it.box] = max(per_box.get(it.box, 0), c)
+        # every item of a box shares the box's cells: the union over its items
+        for bidx in per_box:
+            xs = [it.particles.x for it in wl.items if it.box == bidx]
+            per_box[bidx] = touched_cells(np.concatenate(xs, axis=1), wl.boxes[bidx].n) if len(xs) > 1 \
+                else per_box[bidx]
+        log(f"[bench] {name}: inputs in {time.perf_counter() - t0:.1f} s")
+        wcfg = dict(cfg)
+        wcfg["channels"] = chans
+        r = time_workload(wl, wcfg, 20, every, torch, B, driver)
+        step_bytes, charged_bytes = workload_bytes(wl, per_box)
+        npart = sum(it.particles.n for it in wl.items)
+        sort_bytes = 132 * npart / every
+        k_ach = charged_bytes / (r["charged_kernel_ms"] * 1e-3) / 1e9
+        s_ach = (step_bytes + sort_bytes) / (r["ms_per_step"] * 1e-3) / 1e9
+        r["roofline"] = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "kernel": "charged-particle run kernel launch", "achieved": k_ach,
+                         "frac": k_ach / HBM_PEAK_GBS, "alg_bytes_per_launch": charged_bytes,
+                         "step_achieved": s_ach, "step_frac": s_ach / HBM_PEAK_GBS,
+                         "alg_bytes_per_step": step_bytes + sort_bytes,
+                         "alg_bytes_per_update": (step_bytes + sort_bytes) / npart}
+        out[name] = r
+        log(f"[bench] {name}: {r['ms_per_step']:.3f} ms/step, {r['value']:.3e} updates/s, charged kernel "
+            f"{r['charged_kernel_ms']:.3f} ms ({k_ach:.0f} GB/s), step {s_ach:.0f} GB/s")
+        del wl
+        torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(wl, target_s=15.0):
+def spectra_leg(torch, B, driver, inputs, steps=10):
+    """The Lagrangian spectral update on the paper's particle workload shape
+    (Sec. 4.2 and Table 1: 160^3 cells x 4 particles = 16 384 000 particles,
+    128 spectral points each, float64): one call per step for every particle.
+    Algorithmic bytes per step: every spectral value read and written once
+    (2 arrays x 128 x 8 B x 2), each particle's position read once (float32
+    form: 16 B), and each touched cell's B, gas velocity and divergence read
+    once (7 x 8 B)."""
+    t0 = time.perf_counter()
+    wl = inputs.spectra_box(n=160, ppc=4, nb=128, steps=steps)
+    cells = touched_cells(wl.items[0].particles.x, wl.boxes[0].n)
+    log(f"[bench] spectra: inputs in {time.perf_counter() - t0:.1f} s")
+    run = driver.Run(wl, prec=B.PL_F32_OFFSET, algo=B.PL_ALGO_PLAIN, spectra=True, spectra_sets=1,
+                     sort_buffers=False, channels=[])
+    try:
+        npart = wl.items[0].particles.n
+        nb = len(wl.notes["eng0"])
+        ev = lambda: torch.cuda.Event(enable_timing=True)
+        for _ in range(2):
+            run.spectra(cr=1e-4, u_rad=0.0, ub=0.5)
+        pairs = []
+        for _ in range(steps):
+            a, b = ev(), ev()
+            a.record(run.stream)
+            run.spectra(cr=1e-4, u_rad=0.0, ub=0.5)
+            b.record(run.stream)
+            pairs.append((a, b))
+        torch.cuda.synchronize()
+        if run.sync() != B.PL_OK:
+            raise RuntimeError("device reported an error in the spectral update")
+        ms = sorted(a.elapsed_time(b) for a, b in pairs)[len(pairs) // 2]
+        alg = npart * (2 * nb * 8 * 2 + 16) + cells * 7 * 8
+        ach = alg / (ms * 1e-3) / 1e9
+        r = {"workload": "160^3 box, 4 particles per cell (16 384 000), 128 spectral points each, float64 spectra, "
+                         "turbulent B and gas velocity, random four-divergence (rms 0.1)",
+             "particles": npart, "bins": nb, "ms_per_step": ms, "value": npart / (ms * 1e-3),
+             "unit": "particle-spectra/s",
+             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": ach / HBM_PEAK_GBS, "alg_bytes_per_launch": alg,
+                          "kernel": "pl::k_spectra<1, 2, 3>"},
+             "paper_context": "Particles_Spectra: 190 ms per step for 16.4 M particles on one A100 (Table 1)"}
+        log(f"[bench] spectra: {ms:.3f} ms/step, {ach:.0f} GB/s algorithmic")
+        return r
+    finally:
+        run.close()
+        del run
+        torch.cuda.empty_cache()
+
+
+def boundary_leg(wl, run_kw, torch, B, driver):
+    """Deletion at open boundaries and the holes-and-fillers compaction on the
+    headline's 2^24 particles (float32 form), all three dimensions open with
+    two ghost layers: one synchronous call, timed on the host clock.
+    Algorithmic bytes: each particle's cell read once, and every moved
+    particle's arrays read and written once (cell, offsets, u, w, id: 40 B)."""
+    run = driver.Run(wl, **run_kw)
+    try:
+        run.sort()
+        run.sync()
+        n0 = run.items[0].p.n
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        removed = run.boundary((1, 1, 1), 2)[0]
+        ms = (time.perf_counter() - t0) * 1e3
+        moved = min(removed, run.items[0].p.n)
+        alg = 4 * n0 + 2 * 40 * moved
+        return {"particles": n0, "removed": removed, "ms": ms, "value": n0 / (ms * 1e-3),
+                "unit": "particles/s", "alg_bytes": alg, "achieved_GBs": alg / (ms * 1e-3) / 1e9,
+                "note": "one call, host clock (kernels, the count read-back and the stream synchronisation)"}
+    finally:
+        run.close()
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, target_s=12.0):
     """The float64 oracle on the host cores, on a bounded sample of the same
     workload: the first `ns` particles (same fields, grid, dt), whole steps of
-    gather + push + deposit."""
-    import numpy as np
-
+    gather + push + deposit, with every thread and with one.  The oracle's
+    push runs on all threads (OpenMP over particles); its deposit is a serial
+    loop in particle order, so the all-thread rate is not a per-core rate
+    times the core count."""
     import oracle
     it = wl.items[0].particles
     box = wl.boxes[0]
     ns = 1 << 20
-    x = np.ascontiguousarray(it.x[:, :ns])
-    u = np.ascontiguousarray(it.u[:, :ns])
-    w = np.ascontiguousarray(it.w[:ns])
-    steps = 0
-    t_total = 0.0
-    while t_total < target_s and steps < 50:
-        mom = oracle.new_moments(box.n, oracle.LORENTZ)
-        mom["eng"] = None
-        t0 = time.perf_counter()
-        oracle.step(3, box.n, oracle.TSC, (oracle.LORENTZ, 1.0, 1.0, 0.0), x, u, w, box.fields, wl.dt,
-                    moments=mom)
-        t_total += time.perf_counter() - t0
-        steps += 1
-    return {"value": ns * steps / t_total, "unit": "particle-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"first {ns} of the 2^24 particles, {steps} full steps (gather+push+deposit of rho,J,F) "
-                      f"on the 128^3 turbulent fields, {t_total:.1f} s of CPU time"}
+
+    def rate(threads, budget):
+        oracle.set_threads(threads)
+        x = np.ascontiguousarray(it.x[:, :ns])
+        u = np.ascontiguousarray(it.u[:, :ns])
+        w = np.ascontiguousarray(it.w[:ns])
+        steps, t_total = 0, 0.0
+        while t_total < budget and steps < 50:
+            mom = oracle.new_moments(box.n, oracle.LORENTZ)
+            mom["eng"] = None
+            t0 = time.perf_counter()
+            oracle.step(3, box.n, oracle.TSC, (oracle.LORENTZ, 1.0, 1.0, 0.0), x, u, w, box.fields, wl.dt,
+                        moments=mom)
+            t_total += time.perf_counter() - t0
+            steps += 1
+        return ns * steps / t_total, steps, t_total
+
+    cores = os.cpu_count() or 1
+    allv, asteps, at = rate(cores, target_s)
+    used = oracle.num_threads()
+    onev, osteps, ot = rate(1, target_s / 2)
+    oracle.set_threads(cores)
+    return {"value": allv, "unit": "particle-updates/s", "cores": used, "kind": "oracle",
+            "sample": f"first {ns} of the 2^24 particles, {asteps} full steps (gather+push+deposit of rho,J,F) "
+                      f"on the 128^3 turbulent fields, {at:.1f} s; the push runs on {used} threads, the "
+                      f"deposit serially",
+            "one_thread": {"value": onev, "steps": osteps, "seconds": ot},
+            "cpu_model": cpu_model()}
 
 
 def main():
@@ -195,7 +379,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tiled", action="store_true")
-    ap.add_argument("--extra", action="store_true", help="also time the clumped and batched workloads")
+    ap.add_argument("--no-extra", action="store_true", help="skip the clumped and batched workloads")
+    ap.add_argument("--no-spectra", action="store_true", help="skip the spectral update leg")
+    ap.add_argument("--no-boundary", action="store_true", help="skip the open-boundary leg")
     ap.add_argument("--eager", action="store_true", help="launch steps without hipGraph replay")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -250,6 +436,7 @@ def main():
     if head_cfg["algo"] == B.PL_ALGO_RUNS and (head["stats"][4] == 0 or head["stats"][5] != 0):
         raise RuntimeError(f"the run-based kernel did not take the timed steps: stats {head['stats']}")
     achieved = head["alg_bytes"] / (head["kernel_ms"] * 1e-3) / 1e9
+    step_gbs = (head["alg_bytes"] + 132 * npart / every) / (head["ms_per_step"] * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
@@ -272,6 +459,14 @@ def main():
                         "bank_conflict_ms_per_cu": ins["lds_conflict_ms_per_cu"],
                         "bank_conflict_frac": ins["lds_conflict_ms_per_cu"] / head["kernel_ms"]},
             }
+    # float32 error table of the same kernel sources (written by the whole-grid
+    # parity test of the benchmarked variant)
+    error_table = None
+    if os.path.exists(ERR_FILE):
+        with open(ERR_FILE) as fh:
+            et = json.load(fh)
+        if et.get("src_digest") == src_digest():
+            error_table = et
     sort_name = {B.PL_KEY_TILE: "tile", B.PL_KEY_TILE_CELL: "tile+cell", B.PL_KEY_TILE_RANK: "tile+rank",
                  B.PL_KEY_TILE_RUN: "run-order"}.get(head_cfg["key_mode"], str(head_cfg["key_mode"]))
     out = {
@@ -298,8 +493,11 @@ def main():
                    "sort_ms": head["sort_ms"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel_name(head_cfg, B),
-                     "kernel_ms": head["kernel_ms"], "alg_bytes_per_launch": head["alg_bytes"]},
+                     "kernel_ms": head["kernel_ms"], "alg_bytes_per_launch": head["alg_bytes"],
+                     # the whole step (moment zeroing and the sort, amortised, included)
+                     "step_achieved": step_gbs, "step_frac": step_gbs / HBM_PEAK_GBS},
         "secondary_ceilings": secondary,
+        "error_table": error_table,
     }
     for name, key in (("f32_tiled", "fp32_tiled"), ("f64_plain", "fp64_plain"), ("f64_runs", "fp64_runs")):
         if name in results:
@@ -311,12 +509,18 @@ def main():
         out["speedup_f32_over_f64_plain"] = head["updates_per_s"] / results["f64_plain"]["updates_per_s"]
     if "f64_runs" in results:
         out["speedup_f32_over_f64_runs"] = head["updates_per_s"] / results["f64_runs"]["updates_per_s"]
+    if not args.no_boundary:
+        log("[bench] open-boundary deletion and compaction")
+        out["boundary"] = boundary_leg(wl, BC.run_kwargs(head_cfg), torch, B, driver)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on host cores)")
         out["cpu_baseline"] = cpu_baseline(wl)
-    if args.extra:
-        del wl
-        out["extra_workloads"] = extra_workloads(head_cfg, torch, B, driver, inputs)
+    del wl
+    if not args.no_extra:
+        out["workloads"] = extra_workloads(head_cfg, torch, B, driver, inputs)
+    if not args.no_spectra:
+        out["spectra"] = spectra_leg(torch, B, driver, inputs)
     print(json.dumps(out), flush=True)
 
 

@@ -188,12 +188,19 @@ typedef struct {
                                runs[n + ntiles + 2g], and the number of units at
                                runs[n + ntiles + 2 * (ntiles + PL_RUNS_SPLIT_UNITS)]; required by
                                PL_ALGO_RUNS, n < 2^29 */
+    int nbins;              /* spectral points per particle for pl_part_spectra (0: none) */
+    double *eng[2];         /* nullable: energies of each particle's spectral points, particle-major
+                               (eng[s][p * nbins + i]), both buffer sets like x and u: the sort and
+                               the compaction move a particle's row with it */
+    double *chi[2];         /* nullable: number fraction chi = N / n at those energies (Eq. chi),
+                               same layout */
 } pl_particles;
 
 typedef struct {
     const double *E[3];     /* charged particles: electric field (the E of du/dt above) */
     const double *B[3];     /* charged particles: magnetic field */
     const double *vg[3];    /* dust and tracers: gas velocity */
+    const double *divu;     /* pl_part_spectra: four-divergence of the fluid velocity, div_mu u^mu */
 } pl_fields;
 
 typedef struct {
@@ -318,6 +325,71 @@ pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems);
  */
 #define PL_NOALLOC_MAX_NP (1 << 20)
 pl_status pl_sort_noalloc(const pl_init_desc *d, pl_item *items, int nitems);
+
+/*
+ * pl_part_spectra: advance the energy distribution of every particle of
+ * every item with nbins > 0 by one step dt (finite, non-zero): Sec. 2,
+ * Eqs. cr_N to cr_chi with the losses of Eq. rad_losses.  At the particle's
+ * current position the fluid's B, gas velocity vg and four-divergence divu
+ * are sampled with the box's CIC/TSC weights; then, with a = divu / 3,
+ * c_r = s->cr (s->ub |B|^2 + s->u_rad), d tau = dt / gamma_g
+ * (gamma_g = 1 / sqrt(1 - |vg|^2 / c^2)), E = exp(-a d tau) and
+ * phi = (1 - E) / a (d tau when a = 0), each spectral point moves on its
+ * characteristic d eps / d tau = -a eps - c_r eps^2, solved exactly:
+ *     den = 1 + c_r eps phi,  eps <- eps E / den,  chi <- chi den^2 / E,
+ * so chi d eps (the number between neighbouring points) is conserved.
+ * Arithmetic is float64 in both particle forms.  Any species kind; the item
+ * needs f.B, f.vg and f.divu, and p.eng / p.chi of its current set.  One
+ * launch for all items.  Errors: a null or misaligned array, nbins outside
+ * 1..4096, a non-finite or negative coefficient: PL_EINVAL.  A gas speed at
+ * or above c latches PL_ENONFINITE (that particle's spectrum is left as it
+ * was).
+ */
+typedef struct {
+    double cr;        /* loss coefficient per unit energy density (Eq. rad_losses prefactor) */
+    double u_rad;     /* radiation energy density U_rad */
+    double ub;        /* magnetic energy density per |B|^2: U_B = ub |B|^2 (1/2 in Heaviside-Lorentz units) */
+} pl_spectra_desc;
+pl_status pl_part_spectra(pl_ctx *ctx, const pl_item *items, int nitems, double dt, const pl_spectra_desc *s);
+
+/*
+ * pl_part_boundary: delete the particles that left through open boundaries
+ * and compact every item's current set (Sec. 3.2).  A dimension d with
+ * bc->open[d] != 0 keeps bc->ghost (>= 2) layers of boundary cells on each
+ * side: a particle whose cell lies outside the active cells
+ * [ghost, n[d] - ghost) is deleted.  (With a push of less than a cell per
+ * step and this call after every step, no stencil of an active particle
+ * reaches across the periodic seam of an open dimension.)  The compaction is
+ * the paper's holes-and-fillers algorithm: with ndel particles deleted, the
+ * k-th deleted particle below n - ndel (in index order) is overwritten by the
+ * k-th surviving particle at or above n - ndel (in index order), every array
+ * of the set moving together (cell, x, u, w, id and the spectral rows); the
+ * other survivors keep their index.  O(n) work, scratch from pl_part_init.
+ * Synchronous: waits for the stream, then sets items[i].p.n to the new count
+ * and, when removed is not NULL, removed[i] to the number deleted.  An item
+ * that lost particles has its tile offsets marked unsorted (PL_ENOTSORTED
+ * until the next pl_part_sort); p.fp is not moved.  Errors: bad arguments,
+ * ghost < 2 or 2 * ghost >= n[d] in an open dimension: PL_EINVAL.
+ */
+typedef struct {
+    int open[3];      /* nonzero: outflow boundaries on both sides of dimension d */
+    int ghost;        /* boundary cells on each open side (>= 2) */
+} pl_boundary_desc;
+pl_status pl_part_boundary(pl_ctx *ctx, pl_item *items, int nitems, const pl_boundary_desc *bc, int64_t *removed);
+
+/*
+ * pl_part_inject: append k particles to item->p's current set at indices
+ * [n, n + k) (the paper's particles can be injected at run time, Sec. 3.2):
+ * x[3] grid coordinates and u[3] velocities as float64 device arrays
+ * (converted to the storage form as pl_part_pack does), w (nullable: set to
+ * the species weight when the set has weights), id (nullable), eng / chi
+ * (nullable; k * nbins float64, particle-major, when the set has spectra).
+ * cap is the capacity of the caller's arrays (in particles); n + k must not
+ * exceed cap or max_np.  Sets item->p.n to n + k and marks the item unsorted
+ * (PL_ENOTSORTED until the next pl_part_sort).  Asynchronous.
+ */
+pl_status pl_part_inject(pl_ctx *ctx, pl_item *item, int64_t k, const double *x[3], const double *u[3],
+                         const double *w, const uint64_t *id, const double *eng, const double *chi, int64_t cap);
 
 /*
  * pl_part_pack: write item->p's current set from float64 device arrays

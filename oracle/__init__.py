@@ -87,6 +87,8 @@ def lib():
                                     C.POINTER(C.c_long), C.POINTER(C.c_long), C.POINTER(C.c_uint32)]
         L.orc_num_threads.restype = C.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_stable_sort_perm.restype = None
         L.orc_stable_sort_perm.argtypes = [C.c_long, C.POINTER(C.c_uint32), C.POINTER(C.c_long)]
         L.orc_spectra_step.restype = None
@@ -258,6 +260,10 @@ def split_positions(ndim, n, x):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_threads(n):
+    lib().orc_set_threads(int(n))
 
 
 def stable_sort_perm(keys):

@@ -27,6 +27,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads for the particle loops from now on (for single-thread timings). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Grid conventions                                                   */
 /* ------------------------------------------------------------------ */

@@ -88,6 +88,9 @@ void orc_split_position(const orc_box *b, const double x[3], long cell[3], float
 /* Threads the particle loop uses (OpenMP), for reporting timings. */
 int orc_num_threads(void);
 
+/* Set the threads of the particle loops (n > 0), for single-thread timings. */
+void orc_set_threads(int n);
+
 /* Stable sort: perm[r] = index of the particle that lands at rank r. */
 void orc_stable_sort_perm(long np, const uint32_t *key, long *perm);
 

@@ -31,7 +31,8 @@ PL_FUSE_DEPOSIT, PL_ZERO_FIRST, PL_GRAPH, PL_SUMS = 1, 2, 4, 8
 
 EXPORTS = ["pl_part_init", "pl_part_gather_push", "pl_part_deposit", "pl_part_sort", "pl_part_pack",
            "pl_part_unpack", "pl_part_sums", "pl_part_sync", "pl_part_set_stream", "pl_part_stats",
-           "pl_part_finalize", "pl_status_string", "pl_sort_noalloc"]
+           "pl_part_finalize", "pl_status_string", "pl_sort_noalloc", "pl_part_spectra", "pl_part_boundary",
+           "pl_part_inject"]
 
 _vp = C.c_void_p
 
@@ -56,11 +57,11 @@ class pl_init_desc(C.Structure):
 class pl_particles(C.Structure):
     _fields_ = [("n", C.c_int64), ("cur", C.c_int), ("cell", _vp * 2), ("x", (_vp * 3) * 2),
                 ("u", (_vp * 3) * 2), ("w", _vp * 2), ("id", _vp * 2), ("fp", _vp * 3), ("tile_start", _vp),
-                ("runs", _vp)]
+                ("runs", _vp), ("nbins", C.c_int), ("eng", _vp * 2), ("chi", _vp * 2)]
 
 
 class pl_fields(C.Structure):
-    _fields_ = [("E", _vp * 3), ("B", _vp * 3), ("vg", _vp * 3)]
+    _fields_ = [("E", _vp * 3), ("B", _vp * 3), ("vg", _vp * 3), ("divu", _vp)]
 
 
 class pl_moments(C.Structure):
@@ -70,6 +71,14 @@ class pl_moments(C.Structure):
 class pl_item(C.Structure):
     _fields_ = [("box", C.c_int), ("species", C.c_int), ("p", pl_particles), ("f", pl_fields),
                 ("m", pl_moments)]
+
+
+class pl_spectra_desc(C.Structure):
+    _fields_ = [("cr", C.c_double), ("u_rad", C.c_double), ("ub", C.c_double)]
+
+
+class pl_boundary_desc(C.Structure):
+    _fields_ = [("open", C.c_int * 3), ("ghost", C.c_int)]
 
 
 class PLError(RuntimeError):
@@ -94,6 +103,9 @@ def lib():
         L.pl_part_deposit.argtypes = [_vp, P(pl_item), C.c_int, C.c_uint32]
         L.pl_part_sort.argtypes = [_vp, P(pl_item), C.c_int]
         L.pl_sort_noalloc.argtypes = [P(pl_init_desc), P(pl_item), C.c_int]
+        L.pl_part_spectra.argtypes = [_vp, P(pl_item), C.c_int, C.c_double, P(pl_spectra_desc)]
+        L.pl_part_boundary.argtypes = [_vp, P(pl_item), C.c_int, P(pl_boundary_desc), P(C.c_int64)]
+        L.pl_part_inject.argtypes = [_vp, P(pl_item), C.c_int64, P(_vp), P(_vp), _vp, _vp, _vp, _vp, C.c_int64]
         L.pl_part_pack.argtypes = [_vp, P(pl_item), P(_vp), P(_vp)]
         L.pl_part_unpack.argtypes = [_vp, P(pl_item), P(_vp), P(_vp)]
         L.pl_part_sums.argtypes = [_vp, P(pl_item), C.c_int, P(C.c_double)]
@@ -149,6 +161,31 @@ def pl_part_sort(ctx, items, check=True):
     arr, n = _items_arg(items)
     st = lib().pl_part_sort(ctx, arr, n)
     return _check(st, "pl_part_sort") if check else st
+
+
+def pl_part_spectra(ctx, items, dt, cr, u_rad=0.0, ub=0.5, check=True):
+    arr, n = _items_arg(items)
+    sd = pl_spectra_desc(float(cr), float(u_rad), float(ub))
+    st = lib().pl_part_spectra(ctx, arr, n, float(dt), C.byref(sd))
+    return _check(st, "pl_part_spectra") if check else st
+
+
+def pl_part_boundary(ctx, items, open_dims, ghost, check=True):
+    """Returns (status, removed per item); items' p.n are updated in place."""
+    arr, n = _items_arg(items)
+    bc = pl_boundary_desc((C.c_int * 3)(*[int(v) for v in open_dims]), int(ghost))
+    removed = (C.c_int64 * n)()
+    st = lib().pl_part_boundary(ctx, arr, n, C.byref(bc), removed)
+    if check:
+        _check(st, "pl_part_boundary")
+    return st, list(removed)
+
+
+def pl_part_inject(ctx, item, k, x, u, w=None, id=None, eng=None, chi=None, cap=None, check=True):
+    """x, u: three device pointers each (x[2] may be None in 2D)."""
+    st = lib().pl_part_inject(ctx, C.byref(item), int(k), _ptr3(x), _ptr3(u), w, id, eng, chi,
+                              int(cap if cap is not None else item.p.n + k))
+    return _check(st, "pl_part_inject") if check else st
 
 
 def pl_sort_noalloc(desc, items, check=True):

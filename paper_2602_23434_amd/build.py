@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpl.so")
 SOURCES = ["pl_api.hip", "k_util.hip", "k_step_f32.hip", "k_step_f64.hip", "k_runs_f32.hip", "k_runs_f64.hip",
-           "k_sort.hip"]
+           "k_sort.hip", "k_lp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -252,8 +252,29 @@ __global__ void k_permute_all(const uint32_t *__restrict__ perm, int np, PermArr
     }
 }
 
+// Spectral rows (nb float64 per particle, particle-major): destination row r
+// takes source row perm[r]; one wave per row.
+__global__ __launch_bounds__(256) void k_permute_rows(const uint32_t *perm, int np, int nb, const double *src0,
+                                                      double *dst0, const double *src1, double *dst1)
+{
+    const int lane = threadIdx.x & 63;
+    for (int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < np; r += (gridDim.x * blockDim.x) >> 6) {
+        const long s = (long)perm[r] * nb, d = (long)r * nb;
+        for (int i = lane; i < nb; i += 64) {
+            dst0[d + i] = src0[s + i];
+            dst1[d + i] = src1[s + i];
+        }
+    }
+}
+
 static void permute_arrays(Ctx *c, const SortArgs &a, const uint32_t *perm, int grid)
 {
+    if (a.nb > 0) {
+        const int g = std::max(1, std::min((a.np + 3) / 4, 64 * c->num_cu));
+        hipLaunchKernelGGL(k_permute_rows, dim3(g), dim3(256), 0, c->stream, perm, a.np, a.nb, a.rsrc[0], a.rdst[0],
+                           a.rsrc[1], a.rdst[1]);
+        c->stats[0]++;
+    }
     PermArrays pa;
     memset(&pa, 0, sizeof(pa));
     pa.n = a.narrays;

@@ -136,7 +136,7 @@ void free_ctx(Ctx *c)
 // Item validation and descriptor construction
 // ---------------------------------------------------------------------------
 
-enum Mode { MODE_STEP, MODE_DEPOSIT, MODE_QUERY };  // QUERY: sort, pack, sums
+enum Mode { MODE_STEP, MODE_DEPOSIT, MODE_QUERY, MODE_SPECTRA };  // QUERY: sort, pack, sums, boundary
 
 pl_status make_desc(const Ctx *c, const pl_item &it, double dt, Mode mode, bool deposit, ItemDesc &D)
 {
@@ -166,6 +166,17 @@ pl_status make_desc(const Ctx *c, const pl_item &it, double dt, Mode mode, bool 
         if (!chk(p.fp[a], es, false)) return PL_EINVAL;
     if (d.algo != PL_ALGO_PLAIN && !chk(p.tile_start, 4, true)) return PL_EINVAL;
     if (d.algo == PL_ALGO_RUNS && !chk(p.runs, 4, true)) return PL_EINVAL;
+    if (!chk(p.id[cur], 8, false)) return PL_EINVAL;
+    // spectral rows: both arrays or neither, float64 aligned
+    if (p.nbins < 0 || p.nbins > kMaxBins) return PL_EINVAL;
+    if ((p.eng[cur] != nullptr) != (p.chi[cur] != nullptr)) return PL_EINVAL;
+    if (!chk(p.eng[cur], 8, false) || !chk(p.chi[cur], 8, false)) return PL_EINVAL;
+    if (mode == MODE_SPECTRA) {
+        if (p.nbins < 1 || !chk(p.eng[cur], 8, need) || !chk(p.chi[cur], 8, need)) return PL_EINVAL;
+        for (int a = 0; a < 3; ++a)
+            if (!chk(it.f.B[a], 8, true) || !chk(it.f.vg[a], 8, true)) return PL_EINVAL;
+        if (!chk(it.f.divu, 8, true)) return PL_EINVAL;
+    }
 
     // fields the kind reads (only when pushing)
     if (mode == MODE_STEP) {
@@ -229,8 +240,14 @@ pl_status make_desc(const Ctx *c, const pl_item &it, double dt, Mode mode, bool 
         D.vg[a] = it.f.vg[a];
     }
     D.w = p.w[cur];
+    D.id = p.id[cur];
+    D.dt = dt;
     D.tile_start = p.tile_start;
     D.runs = p.runs;
+    D.nb = p.eng[cur] ? p.nbins : 0;
+    D.eng = p.eng[cur];
+    D.chi = p.chi[cur];
+    D.divu = it.f.divu;
     D.nslot = 0;
     for (int ch = 0; ch < kMaxCh; ++ch) {
         D.M[ch] = M[ch];
@@ -556,6 +573,15 @@ pl_status sort_args(const Ctx *c, const pl_item &it, SortArgs &a)
         ok = ok && add(p.id[cur], p.id[nxt], 8);
         if (p.id[cur] && !aligned(p.id[cur], 8)) ok = false;
         if (!ok) return PL_EINVAL;
+        if (D.nb > 0) {
+            // the spectral rows move with their particles
+            if (!p.eng[nxt] || !p.chi[nxt] || !aligned(p.eng[nxt], 8) || !aligned(p.chi[nxt], 8)) return PL_EINVAL;
+            a.nb = D.nb;
+            a.rsrc[0] = p.eng[cur];
+            a.rsrc[1] = p.chi[cur];
+            a.rdst[0] = p.eng[nxt];
+            a.rdst[1] = p.chi[nxt];
+        }
     }
     return PL_OK;
 }
@@ -584,6 +610,98 @@ pl_status pl_part_sort(pl_ctx *ctx, pl_item *items, int nitems)
             c->fp_stale.push_back(fp);
         }
     }
+    return PL_OK;
+}
+
+pl_status pl_part_spectra(pl_ctx *ctx, const pl_item *items, int nitems, double dt, const pl_spectra_desc *sd)
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || !sd || !items || nitems < 1 || nitems > c->d.max_items) return PL_EINVAL;
+    if (!isfinite(dt) || dt == 0.0) return PL_EINVAL;
+    if (!isfinite(sd->cr) || !isfinite(sd->u_rad) || !isfinite(sd->ub) || sd->cr < 0.0 || sd->u_rad < 0.0 ||
+        sd->ub < 0.0)
+        return PL_EINVAL;
+    std::vector<ItemDesc> host(nitems);
+    int units = 0;
+    for (int i = 0; i < nitems; ++i) {
+        pl_status st = make_desc(c, items[i], dt, MODE_SPECTRA, false, host[i]);
+        if (st != PL_OK) return st;
+        host[i].unit_begin = units;
+        host[i].nunits = host[i].np > 0 ? (host[i].np + 255) / 256 : 0;
+        units += host[i].nunits;
+    }
+    pl_status st = upload_table(c, host, c->table);
+    if (st != PL_OK) return st;
+    hipError_t e = launch_spectra(c, c->table, host, sd->cr, sd->u_rad, sd->ub);
+    if (e == hipErrorInvalidConfiguration) return PL_EUNSUPPORTED;
+    return e == hipSuccess ? PL_OK : PL_EHIP;
+}
+
+pl_status pl_part_boundary(pl_ctx *ctx, pl_item *items, int nitems, const pl_boundary_desc *bc, int64_t *removed)
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || !bc || !items || nitems < 1 || nitems > c->d.max_items) return PL_EINVAL;
+    std::vector<ItemDesc> descs(nitems);
+    for (int i = 0; i < nitems; ++i) {
+        pl_status st = make_desc(c, items[i], 1.0, MODE_QUERY, false, descs[i]);
+        if (st != PL_OK) return st;
+        for (int d = 0; d < c->d.ndim; ++d)
+            if (bc->open[d] && (bc->ghost < 2 || 2 * bc->ghost >= descs[i].n[d])) return PL_EINVAL;
+    }
+    for (int i = 0; i < nitems; ++i) {
+        int64_t keep = 0, gone = 0;
+        if (launch_boundary(c, descs[i], *bc, c->d.ndim, &keep, &gone) != hipSuccess) return PL_EHIP;
+        items[i].p.n = keep;
+        if (removed) removed[i] = gone;
+        const void *fp = items[i].p.fp[0];
+        if (gone > 0 && fp && std::find(c->fp_stale.begin(), c->fp_stale.end(), fp) == c->fp_stale.end()) {
+            if (c->fp_stale.size() >= c->fp_stale.capacity()) c->fp_stale.erase(c->fp_stale.begin());
+            c->fp_stale.push_back(fp);
+        }
+    }
+    return PL_OK;
+}
+
+pl_status pl_part_inject(pl_ctx *ctx, pl_item *item, int64_t k, const double *x[3], const double *u[3],
+                         const double *w, const uint64_t *id, const double *eng, const double *chi, int64_t cap)
+{
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!c || !item || !x || !u || k < 0) return PL_EINVAL;
+    ItemDesc D;
+    pl_status st = make_desc(c, *item, 1.0, MODE_QUERY, false, D);
+    if (st != PL_OK) return st;
+    const int64_t n = item->p.n;
+    if (n + k > cap || n + k > c->max_np) return PL_EINVAL;
+    if (k == 0) return PL_OK;
+    // the destination set must hold every array the item carries
+    const int cur = item->p.cur;
+    if ((c->d.prec == PL_F32_OFFSET && !item->p.cell[cur]) || !item->p.u[cur][0]) return PL_EINVAL;
+    for (int a = 0; a < c->d.ndim; ++a)
+        if (!item->p.x[cur][a]) return PL_EINVAL;
+    const double *xs[3] = {nullptr, nullptr, nullptr}, *us[3];
+    for (int a = 0; a < 3; ++a) {
+        if (a < c->d.ndim) {
+            if (!x[a] || !aligned(x[a], 8)) return PL_EINVAL;
+            xs[a] = x[a];
+        }
+        if (!u[a] || !aligned(u[a], 8)) return PL_EINVAL;
+        us[a] = u[a];
+    }
+    if (!aligned(w, 8) || !aligned(id, 8) || !aligned(eng, 8) || !aligned(chi, 8)) return PL_EINVAL;
+    if (D.nb > 0 && (!eng || !chi)) return PL_EINVAL;
+    // positions and velocities through the pack kernel, at [n, n + k)
+    const size_t es = c->d.prec == PL_F64 ? 8 : 4;
+    ItemDesc T = D;
+    T.np = (int)k;
+    if (T.cell) T.cell += n;
+    for (int a = 0; a < 3; ++a) {
+        if (T.x[a]) T.x[a] = static_cast<char *>(T.x[a]) + n * es;
+        T.u[a] = static_cast<char *>(T.u[a]) + n * es;
+    }
+    if (launch_pack(c, T, c->d.prec, c->d.ndim, xs, us) != hipSuccess) return PL_EHIP;
+    const pl_species_desc &sp = c->d.species[item->species];
+    if (launch_inject_rest(c, D, k, w, D.w != nullptr, sp.weight, id, D.id, eng, chi) != hipSuccess) return PL_EHIP;
+    item->p.n = n + k;
     return PL_OK;
 }
 

@@ -69,10 +69,16 @@ struct ItemDesc {
     void *fp[3];
     int32_t *tile_start;
     int32_t *runs;           // run table (PL_ALGO_RUNS)
+    uint64_t *id;            // nullable: particle ids (current set)
+    double dt;               // the call's time step
+    int nb;                  // spectral points per particle (0: none)
+    double *eng;             // spectral energies, particle-major (current set)
+    double *chi;             // spectral number fractions, same layout
     // fields
     const double *E[3];
     const double *B[3];
     const double *vg[3];
+    const double *divu;      // four-divergence of the fluid velocity (spectra)
     // moments
     double *M[kMaxCh];
     int slot[kMaxCh];        // LDS slot of each active channel, -1 if inactive
@@ -150,6 +156,19 @@ hipError_t launch_grid_sums(Ctx *c, const ItemDesc &it, double *out8);
 hipError_t launch_pack(Ctx *c, const ItemDesc &it, int prec, int ndim, const double *x[3], const double *u[3]);
 hipError_t launch_unpack(Ctx *c, const ItemDesc &it, int prec, int ndim, double *x[3], double *u[3]);
 
+// Lagrangian-particle extras (k_lp.hip)
+constexpr int kMaxBins = 4096;
+hipError_t launch_spectra(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc> &host, double cr,
+                          double u_rad, double ub);
+// Deletion at open boundaries and compaction of one item; writes the new
+// count and the number removed (int64) to host memory, synchronously.
+hipError_t launch_boundary(Ctx *c, const ItemDesc &it, const pl_boundary_desc &bc, int ndim, int64_t *keep,
+                           int64_t *removed);
+// Weights, ids and spectral rows of k injected particles at [it.np, it.np + k)
+// (positions and velocities go through launch_pack); marks the item unsorted.
+hipError_t launch_inject_rest(Ctx *c, const ItemDesc &it, int64_t k, const double *w, bool has_w, double wdef,
+                              const uint64_t *id, uint64_t *id_dst, const double *eng, const double *chi);
+
 // Sort (k_sort.hip)
 struct SortArgs {
     int prec, ndim, key_mode;
@@ -166,6 +185,10 @@ struct SortArgs {
     int narrays;
     int32_t *tile_start;
     int32_t *runs;                   // nullable: run table to build (PL_ALGO_RUNS)
+    // spectral rows (nb doubles per particle) moved with the particles
+    int nb;
+    const double *rsrc[2];
+    double *rdst[2];
 };
 hipError_t launch_sort(Ctx *c, const SortArgs &a);
 // The same sort with its scratch in the library's fixed device array (set up

@@ -29,7 +29,7 @@ class Run:
 
     def __init__(self, wl, prec=B.PL_F64, algo=B.PL_ALGO_PLAIN, key_mode=None, block=0,
                  tile=None, c=1.0, weights=True, ids=True, fp=False, eng=True, sort_buffers=True,
-                 tune_cache=None, channels=None, device="cuda"):
+                 tune_cache=None, channels=None, device="cuda", spectra=False, spectra_sets=2, capacity=None):
         import torch
 
         self.torch = torch
@@ -72,7 +72,8 @@ class Run:
         d.nspecies = ns
         d.species = self._species
         d.max_items = len(wl.items)
-        d.max_np = max(1, max(it.particles.n for it in wl.items))
+        self.capacity = [max(it.particles.n, capacity or 0) for it in wl.items]
+        d.max_np = max(1, max(self.capacity))
         d.block = block
         d.stream = self.stream.cuda_stream
         d.tune_cache = tune_cache.encode() if tune_cache else None
@@ -91,7 +92,7 @@ class Run:
                 bx = wl.boxes[it.box]
                 sp = wl.species[it.species]
                 kind = KIND[sp.kind]
-                n = it.particles.n
+                n = self.capacity[i]
                 sets = []
                 for s in range(2 if sort_buffers else 1):
                     st = {
@@ -110,7 +111,19 @@ class Run:
                     # run table sized for one tile per cell (the most tiles a box can have)
                     "runs": (torch.zeros(B.runs_len(n, bx.n[0] * bx.n[1] * bx.n[2]), dtype=torch.int32, device=self.dev)
                              if algo == B.PL_ALGO_RUNS else None),
+                    "eng": None, "chi": None,
                 }
+                if spectra:
+                    # every particle starts with the workload's template spectrum
+                    e0 = torch.from_numpy(np.ascontiguousarray(wl.notes["eng0"])).to(self.dev)
+                    c0 = torch.from_numpy(np.ascontiguousarray(wl.notes["chi0"])).to(self.dev)
+                    nbins = e0.shape[0]
+                    extra["eng"] = [torch.empty((n, nbins), dtype=torch.float64, device=self.dev)
+                                    for _ in range(spectra_sets)]
+                    extra["chi"] = [torch.empty((n, nbins), dtype=torch.float64, device=self.dev)
+                                    for _ in range(spectra_sets)]
+                    extra["eng"][0].copy_(e0.expand(n, nbins))
+                    extra["chi"][0].copy_(c0.expand(n, nbins))
                 self.parts.append({"sets": sets, **extra})
                 shape = (bx.n[2], bx.n[1], bx.n[0])
                 # every channel of the item is a view of one block, so zeroing the
@@ -145,10 +158,11 @@ class Run:
                 self._fill_item(i)
                 # initial state: float64 positions and velocities -> current set
                 w = torch.from_numpy(it.particles.w).to(self.dev)
+                np0 = it.particles.n
                 if weights:
-                    sets[0]["w"].copy_(w.to(fdt))
+                    sets[0]["w"][:np0].copy_(w.to(fdt))
                 if ids:
-                    sets[0]["id"].copy_(torch.from_numpy(it.particles.id.astype(np.int64)).to(self.dev))
+                    sets[0]["id"][:np0].copy_(torch.from_numpy(it.particles.id.astype(np.int64)).to(self.dev))
             self.stream.synchronize()
         self.load_state([(it.particles.x, it.particles.u) for it in wl.items])
 
@@ -162,6 +176,11 @@ class Run:
         p = self.parts[i]
         rec.p.n = it.particles.n
         rec.p.cur = 0
+        if p["eng"] is not None:
+            rec.p.nbins = p["eng"][0].shape[1]
+            for s in range(len(p["eng"])):
+                rec.p.eng[s] = _ptr(p["eng"][s])
+                rec.p.chi[s] = _ptr(p["chi"][s])
         for s, st in enumerate(p["sets"]):
             rec.p.cell[s] = _ptr(st["cell"])
             for a in range(3):
@@ -181,6 +200,11 @@ class Run:
                 rec.f.B[a] = _ptr(f["B"][a])
             else:
                 rec.f.vg[a] = _ptr(f["vg"][a])
+            if "divu" in f:
+                rec.f.B[a] = _ptr(f["B"][a])
+                rec.f.vg[a] = _ptr(f["vg"][a])
+        if "divu" in f:
+            rec.f.divu = _ptr(f["divu"])
         mo = self.moms[i]
         rec.m.rho = _ptr(mo.get("rho"))
         for a in range(3):
@@ -215,6 +239,38 @@ class Run:
     def sort(self):
         return B.pl_part_sort(self.ctx, self.items)
 
+    def spectra(self, dt=None, cr=1e-4, u_rad=0.0, ub=0.5):
+        dt = self.wl.dt if dt is None else dt
+        return B.pl_part_spectra(self.ctx, self.items, dt, cr, u_rad, ub)
+
+    def boundary(self, open_dims, ghost):
+        """Delete particles outside the active cells of the open dimensions and
+        compact; returns the number removed per item."""
+        return B.pl_part_boundary(self.ctx, self.items, open_dims, ghost)[1]
+
+    def inject(self, i, x, u, w=None, ids=None, eng=None, chi=None):
+        """Append particles to item i from float64 numpy arrays x, u (3, k)."""
+        torch = self.torch
+        k = x.shape[1]
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.dev) if a is not None else None
+        xd = [dev(x[a]) for a in range(3)]
+        ud = [dev(u[a]) for a in range(3)]
+        wd, idd = dev(w), dev(ids.astype(np.int64) if ids is not None else None)
+        ed, cd = dev(eng), dev(chi)
+        torch.cuda.synchronize()
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        st = B.pl_part_inject(self.ctx, self.items[i], k, [ptr(t) for t in xd[: self.ndim]], [ptr(t) for t in ud],
+                              ptr(wd), ptr(idd), ptr(ed), ptr(cd), cap=self.capacity[i])
+        self.stream.synchronize()
+        return st
+
+    def spectra_state(self, i):
+        """(eng, chi) of item i's current set as (n, nbins) float64 numpy arrays."""
+        self.stream.synchronize()
+        cur = self.items[i].p.cur
+        n = self.items[i].p.n
+        return self.parts[i]["eng"][cur][:n].cpu().numpy(), self.parts[i]["chi"][cur][:n].cpu().numpy()
+
     def sync(self):
         return B.pl_part_sync(self.ctx)
 
@@ -224,7 +280,7 @@ class Run:
     def state(self, i):
         """(x, u, id) of item i as float64 numpy arrays (current set)."""
         torch = self.torch
-        n = self.wl.items[i].particles.n
+        n = int(self.items[i].p.n)
         with torch.cuda.stream(self.stream):
             x = [torch.zeros(n, dtype=torch.float64, device=self.dev) for _ in range(3)]
             u = [torch.zeros(n, dtype=torch.float64, device=self.dev) for _ in range(3)]
@@ -235,7 +291,7 @@ class Run:
         ids = self.parts[i]["sets"][cur]["id"]
         xs = np.stack([t.cpu().numpy() for t in x])
         us = np.stack([t.cpu().numpy() for t in u])
-        idn = ids.cpu().numpy().astype(np.uint64) if ids is not None else None
+        idn = ids[:n].cpu().numpy().astype(np.uint64) if ids is not None else None
         return xs, us, idn, st
 
     def raw(self, i):

@@ -58,8 +58,10 @@ int main(void) {
   O(pl_init_desc, block) O(pl_init_desc, stream) O(pl_init_desc, tune_cache)
   S(pl_particles) O(pl_particles, cur) O(pl_particles, cell) O(pl_particles, x) O(pl_particles, u)
   O(pl_particles, w) O(pl_particles, id) O(pl_particles, fp) O(pl_particles, tile_start)
-  O(pl_particles, runs)
-  S(pl_fields) O(pl_fields, B) O(pl_fields, vg)
+  O(pl_particles, runs) O(pl_particles, nbins) O(pl_particles, eng) O(pl_particles, chi)
+  S(pl_fields) O(pl_fields, B) O(pl_fields, vg) O(pl_fields, divu)
+  S(pl_spectra_desc) O(pl_spectra_desc, u_rad) O(pl_spectra_desc, ub)
+  S(pl_boundary_desc) O(pl_boundary_desc, ghost)
   S(pl_moments) O(pl_moments, J) O(pl_moments, F) O(pl_moments, eng)
   S(pl_item) O(pl_item, p) O(pl_item, f) O(pl_item, m)
   printf("runs_len %lld\n", (long long)PL_RUNS_LEN(1000, 64));
@@ -151,6 +153,13 @@ def test_null_context_calls_are_rejected(lib):
     assert lib.pl_part_deposit(None, C.byref(item), 1, 0) == B.PL_EINVAL
     assert lib.pl_part_sort(None, C.byref(item), 1) == B.PL_EINVAL
     assert lib.pl_part_sync(None) == B.PL_EINVAL
+    sd = B.pl_spectra_desc(1.0, 0.0, 0.5)
+    assert lib.pl_part_spectra(None, C.byref(item), 1, 0.05, C.byref(sd)) == B.PL_EINVAL
+    bc = B.pl_boundary_desc((C.c_int * 3)(1, 0, 0), 2)
+    assert lib.pl_part_boundary(None, C.byref(item), 1, C.byref(bc), None) == B.PL_EINVAL
+    x3 = (C.c_void_p * 3)()
+    assert lib.pl_part_inject(None, C.byref(item), 1, x3, x3, None, None, None, None, 1) == B.PL_EINVAL
+    assert lib.pl_sort_noalloc(None, C.byref(item), 1) == B.PL_EINVAL
     out = (C.c_int64 * B.PL_NSTATS)()
     assert lib.pl_part_stats(None, out, B.PL_NSTATS) == B.PL_EINVAL
     assert lib.pl_part_init(None, None) == B.PL_EINVAL

@@ -94,8 +94,10 @@ def test_bench_variant_f32_whole_grid(mods, turb32):
     table = _cmp.state_error_stats(gx, gu, gid, ores[0]["x"], ores[0]["u"], wl.boxes[0].n, 3)
     merr = _cmp.moment_errors(run.moments(0), ores[0]["moments"], ores[0]["abs"])
     assert set(merr) == {"rho", "J0", "J1", "J2", "F0", "F1", "F2"}, merr.keys()
+    from paper_2602_23434_amd import profiling
     out = {"workload": "turbulent 32^3, 262107 particles, 20 steps, sort every 8, float32 run kernel "
                        "(8^3 tiles, rho J F) vs float64 oracle, every particle and cell",
+           "src_digest": profiling.src_digest(),
            "units": "x: cells; u: |du|/max(|u|, 0.05) per component; deposits: |dM|/A_c per cell",
            "table": {}}
     for k, (mx, rms) in table.items():
