@@ -21,10 +21,8 @@ struct SpecPar {
     double cr, u_rad, ub, inv_c2;
 };
 
-// Streaming accesses to the spectral rows: each value is read and written
-// once per step, so they bypass the caches the field samples use.
-__device__ __forceinline__ double nt_load(gptr<double> p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ void nt_store(double v, gptr<double> p) { __builtin_nontemporal_store(v, p); }
+// The spectral rows are read and written once per step with non-temporal
+// accesses, so they do not displace the fields the sampling reads.
 
 // Cell and float64 offset from the cell centre of particle p, per dimension.
 template <int PREC, int DIM>
@@ -91,10 +89,13 @@ __device__ __forceinline__ void sample_fluid(const ItemDesc &I, int p, double q[
 #pragma unroll
     for (int m = 0; m < 7; ++m) q[m] = 0.0;
     constexpr int SZ = DIM >= 3 ? 3 : 1, SY = DIM >= 2 ? 3 : 1;
-#pragma unroll
+    // one stencil row (three x-neighbours, 21 loads) in flight at a time:
+    // unrolled further the loads would take the registers the streaming
+    // of the spectral rows needs
+#pragma unroll 1
     for (int k = 0; k < SZ; ++k) {
         const int gz = DIM >= 3 ? wrap_cell(c[2] + k - 1, I.n[2]) : 0;
-#pragma unroll
+#pragma unroll 1
         for (int j = 0; j < SY; ++j) {
             const int gy = DIM >= 2 ? wrap_cell(c[1] + j - 1, I.n[1]) : 0;
             const double wyz = w[2][DIM >= 3 ? k : 1] * w[1][DIM >= 2 ? j : 1];
@@ -110,16 +111,159 @@ __device__ __forceinline__ void sample_fluid(const ItemDesc &I, int p, double q[
     }
 }
 
+// W consecutive spectral values of one row (W = 2: one 16-byte access).
+template <int W> struct SpecVec;
+template <> struct SpecVec<1> {
+    typedef double T;
+    __device__ static double get(T v, int) { return v; }
+    __device__ static void set(T &v, int, double x) { v = x; }
+};
+template <> struct SpecVec<2> {
+    typedef double T __attribute__((ext_vector_type(2)));
+    __device__ static double get(T v, int k) { return v[k]; }
+    __device__ static void set(T &v, int k, double x) { v[k] = x; }
+};
+
+// The block's rows, streamed: access a = pass * 256 + threadIdx.x covers
+// values [W a, W a + W) of the rows (all in one row, nb being a multiple of
+// W); kSpecUnroll passes are loaded together, and the next group's loads are
+// issued before the current group is updated and stored.  The first group
+// is loaded by the caller before the fluid sampling, so the block's HBM
+// traffic starts at once.
+template <int W>
+struct SpecStream {
+    using V = SpecVec<W>;
+    using T = typename V::T;
+    typedef __attribute__((address_space(1))) T *P;
+    P eng, chi;
+    long naccess;                     // accesses of the block: cnt * nb / W
+    int nb;
+    T ev[kSpecUnroll], cv[kSpecUnroll];
+    int rr[kSpecUnroll];
+    int row, col;                     // row and first column of this thread's next access
+
+    __device__ void init(gptr<double> e, gptr<double> c, int cnt, int nb_)
+    {
+        eng = (P)e;
+        chi = (P)c;
+        nb = nb_;
+        naccess = (long)cnt * nb / W;
+        const int v = threadIdx.x * W;
+        row = v / nb;
+        col = v % nb;
+    }
+
+    // load the group of passes starting at access a0 (this thread's first)
+    __device__ __forceinline__ void load(long a0)
+    {
+        constexpr int step = kSpecThreads * W;
+        const int srow = step / nb, scol = step % nb;
+#pragma unroll
+        for (int k = 0; k < kSpecUnroll; ++k) {
+            const long a = a0 + (long)k * kSpecThreads;
+            rr[k] = row;
+            if (a < naccess) {
+                ev[k] = __builtin_nontemporal_load(eng + a);
+                cv[k] = __builtin_nontemporal_load(chi + a);
+            }
+            row += srow;
+            col += scol;
+            if (col >= nb) { col -= nb; ++row; }
+        }
+    }
+
+    __device__ __forceinline__ void update(long a0, const double *sE, const double *siE, const double *sb)
+    {
+#pragma unroll
+        for (int k = 0; k < kSpecUnroll; ++k) {
+            const long a = a0 + (long)k * kSpecThreads;
+            if (a < naccess) {
+                const double E = sE[rr[k]], iE = siE[rr[k]], b = sb[rr[k]];
+                T eo, co;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const double e0 = V::get(ev[k], w);
+                    const double den = 1.0 + b * e0;
+                    V::set(eo, w, e0 * E / den);
+                    V::set(co, w, V::get(cv[k], w) * den * den * iE);
+                }
+                __builtin_nontemporal_store(eo, eng + a);
+                __builtin_nontemporal_store(co, chi + a);
+            }
+        }
+    }
+};
+
+template <int W>
+__device__ __forceinline__ void spectra_rows(SpecStream<W> &S, const double *sE, const double *siE,
+                                             const double *sb)
+{
+    constexpr long group = (long)kSpecThreads * kSpecUnroll;
+    for (long a0 = threadIdx.x; a0 < S.naccess; a0 += group) {
+        // the next group's loads go out before this group's update
+        SpecStream<W> nxt = S;
+        const bool more = a0 + group < S.naccess;
+        if (more) nxt.load(a0 + group);
+        S.update(a0, sE, siE, sb);
+        if (more) {
+            S = nxt;
+        }
+    }
+}
+
+// Coefficients of one particle's step: E = exp(-a d tau), 1/E and
+// c_r phi; the identity (1, 1, 0) when the gas moves at c or faster.
+template <int PREC, int SHAPE, int DIM>
+__device__ __forceinline__ void spectra_coef(const ItemDesc &I, int p, const SpecPar &sp, double &E, double &iE,
+                                             double &bphi, int &err)
+{
+    double q[7];
+    sample_fluid<PREC, SHAPE, DIM>(I, p, q, err);
+    const double v2 = fma(q[3], q[3], fma(q[4], q[4], q[5] * q[5])) * sp.inv_c2;
+    const double b2 = fma(q[0], q[0], fma(q[1], q[1], q[2] * q[2]));
+    E = 1.0;
+    iE = 1.0;
+    bphi = 0.0;
+    if (!(v2 < 1.0)) {
+        err |= ERR_NONFINITE;
+        return;
+    }
+    const double dtau = I.dt * sqrt(1.0 - v2);      // d tau = dt / gamma_g
+    const double a = q[6] / 3.0;
+    const double b = sp.cr * fma(sp.ub, b2, sp.u_rad);
+    E = exp(-a * dtau);
+    iE = 1.0 / E;
+    const double phi = a != 0.0 ? -expm1(-a * dtau) / a : dtau;
+    bphi = b * phi;
+}
+
 // One block per 256 particles of one item: each thread samples the fluid at
-// its particle and leaves the step's coefficients in LDS; then the block
-// streams the 256 contiguous spectral rows (particle-major) with one
-// element per thread and pass, several passes in flight.
+// its particle and leaves the step's coefficients in LDS; the block then
+// streams its 256 contiguous spectral rows (particle-major).
+template <int PREC, int SHAPE, int DIM, int W>
+__device__ __forceinline__ void spectra_block(const ItemDesc &I, int p0, int cnt, const SpecPar &sp, double *sE,
+                                              double *siE, double *sb, int &err)
+{
+    SpecStream<W> S;
+    S.init((gptr<double>)I.eng + (long)p0 * I.nb, (gptr<double>)I.chi + (long)p0 * I.nb, cnt, I.nb);
+    S.load(threadIdx.x);
+    {
+        const int t = threadIdx.x;
+        double E = 1.0, iE = 1.0, bphi = 0.0;
+        if (t < cnt) spectra_coef<PREC, SHAPE, DIM>(I, p0 + t, sp, E, iE, bphi, err);
+        sE[t] = E;
+        siE[t] = iE;
+        sb[t] = bphi;
+    }
+    __syncthreads();
+    spectra_rows<W>(S, sE, siE, sb);
+}
+
 template <int PREC, int SHAPE, int DIM>
 __global__ __launch_bounds__(kSpecThreads) void k_spectra(const ItemDesc *__restrict__ items, int nitems, SpecPar sp,
                                                           int *errflags)
 {
-    __shared__ double s_E[kSpecThreads], s_iE[kSpecThreads], s_bphi[kSpecThreads];
-    __shared__ int s_ok[kSpecThreads];
+    __shared__ double s_E[kSpecThreads], s_iE[kSpecThreads], s_b[kSpecThreads];
     const int g = blockIdx.x;
     int iti = 0;
     while (iti + 1 < nitems && items[iti + 1].unit_begin <= g) ++iti;
@@ -128,72 +272,9 @@ __global__ __launch_bounds__(kSpecThreads) void k_spectra(const ItemDesc *__rest
     if (p0 >= I.np || I.nb <= 0) return;                  // uniform
     const int cnt = min(kSpecThreads, I.np - p0);
     int err = 0;
-    {
-        const int t = threadIdx.x;
-        double E = 1.0, iE = 1.0, bphi = 0.0;
-        int ok = 1;
-        if (t < cnt) {
-            double q[7];
-            sample_fluid<PREC, SHAPE, DIM>(I, p0 + t, q, err);
-            const double v2 = fma(q[3], q[3], fma(q[4], q[4], q[5] * q[5])) * sp.inv_c2;
-            const double b2 = fma(q[0], q[0], fma(q[1], q[1], q[2] * q[2]));
-            if (!(v2 < 1.0)) {
-                ok = 0;
-                err |= ERR_NONFINITE;
-            } else {
-                const double dtau = I.dt * sqrt(1.0 - v2);      // d tau = dt / gamma_g
-                const double a = q[6] / 3.0;
-                const double b = sp.cr * fma(sp.ub, b2, sp.u_rad);
-                E = exp(-a * dtau);
-                iE = 1.0 / E;
-                const double phi = a != 0.0 ? -expm1(-a * dtau) / a : dtau;
-                bphi = b * phi;
-            }
-        }
-        s_E[t] = E;
-        s_iE[t] = iE;
-        s_bphi[t] = bphi;
-        s_ok[t] = ok;
-    }
-    __syncthreads();
-    const int nb = I.nb;
-    const long base = (long)p0 * nb;
-    const long total = (long)cnt * nb;
-    gptr<double> eng = (gptr<double>)I.eng + base;
-    gptr<double> chi = (gptr<double>)I.chi + base;
-    // element e = pass * 256 + threadIdx.x of the block's rows; its particle
-    // row and column advance incrementally (no division per element)
-    int row = threadIdx.x / nb, col = threadIdx.x % nb;
-    const int step_rows = kSpecThreads / nb, step_cols = kSpecThreads % nb;
-    for (long e0 = threadIdx.x; e0 < total; e0 += (long)kSpecThreads * kSpecUnroll) {
-        double ev[kSpecUnroll], cv[kSpecUnroll];
-        int rr[kSpecUnroll];
-        int r = row, cl = col;
-#pragma unroll
-        for (int k = 0; k < kSpecUnroll; ++k) {
-            const long e = e0 + (long)k * kSpecThreads;
-            rr[k] = r;
-            if (e < total) {
-                ev[k] = nt_load(eng + e);
-                cv[k] = nt_load(chi + e);
-            }
-            r += step_rows;
-            cl += step_cols;
-            if (cl >= nb) { cl -= nb; ++r; }
-        }
-#pragma unroll
-        for (int k = 0; k < kSpecUnroll; ++k) {
-            const long e = e0 + (long)k * kSpecThreads;
-            if (e < total && s_ok[rr[k]]) {
-                const double den = 1.0 + s_bphi[rr[k]] * ev[k];
-                nt_store(ev[k] * s_E[rr[k]] / den, eng + e);
-                nt_store(cv[k] * den * den * s_iE[rr[k]], chi + e);
-            }
-        }
-        row = r;
-        col = cl;
-    }
-    if (err && threadIdx.x < kSpecThreads) atomicOr(errflags, err);
+    if ((I.nb & 1) == 0) spectra_block<PREC, SHAPE, DIM, 2>(I, p0, cnt, sp, s_E, s_iE, s_b, err);
+    else spectra_block<PREC, SHAPE, DIM, 1>(I, p0, cnt, sp, s_E, s_iE, s_b, err);
+    if (err) atomicOr(errflags, err);
 }
 
 hipError_t launch_spectra(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc> &host, double cr,

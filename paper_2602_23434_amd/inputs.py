@@ -303,11 +303,25 @@ def scalar_field(n, seed, rms, kmax_frac=0.25, slope=-11.0 / 6.0):
     return f * (rms / math.sqrt(float(np.mean(f * f))))
 
 
+def per_cell_positions(rng, ppc, n):
+    """ppc particles in every cell of an n^3 grid, each uniform inside its
+    cell, stored cell by cell (x fastest): how a grid code seeds a fixed
+    number of particles per cell."""
+    nx, ny, nz = n
+    ncell = nx * ny * nz
+    cell = np.repeat(np.arange(ncell, dtype=np.int64), ppc)
+    base = np.stack([cell % nx, (cell // nx) % ny, cell // (nx * ny)]).astype(np.float64)
+    x = base + rng.random((3, cell.shape[0]))
+    for d in range(3):
+        x[d] = _inside(x[d], n[d])
+    return x
+
+
 def spectra_box(n=160, ppc=4, nb=128, steps=10, k=5, divu_rms=0.1, dt=0.05):
     """The paper's Lagrangian-particle workload shape (Sec. 4.2, Table 1): n^3
-    cells with ppc particles per cell (160^3 x 4 = 16 384 000 per GPU), each
-    carrying nb spectral points initialised to the power law of
-    powerlaw_spectrum; turbulent B and gas velocity, and a random
+    cells with ppc particles per cell (160^3 x 4 = 16 384 000 per GPU), seeded
+    cell by cell, each carrying nb spectral points initialised to the power
+    law of powerlaw_spectrum; turbulent B and gas velocity, and a random
     four-divergence field (rms divu_rms) for the adiabatic term.  The spectra
     are returned as one (nb,) template (every particle starts with it)."""
     nn = (n, n, n)
@@ -315,7 +329,7 @@ def spectra_box(n=160, ppc=4, nb=128, steps=10, k=5, divu_rms=0.1, dt=0.05):
     flds["divu"] = scalar_field(nn, SEED_V + 100 + k, divu_rms)
     rng = np.random.default_rng(SEED_P + k)
     npart = ppc * n ** 3
-    x = uniform_positions(rng, npart, nn, 3)
+    x = per_cell_positions(rng, ppc, nn)
     box = Box(ndim=3, n=nn, fields=flds)
     eng, chi = powerlaw_spectrum(nb)
     return Workload(name=f"spectra {n}^3, {npart} particles, {nb} bins", boxes=[box],
