@@ -10,10 +10,11 @@ cell, cell) runs inside the timed loop at the tuned cadence.  The plain float64
 path runs on the same inputs for the speedup, and the run-based float64 path
 and the tiled float32 path beside it.
 
-Each timed step: zero the moment grids, then one fused gather/push/deposit
-launch (a replayed hipGraph) bracketed by HIP events on the library's stream;
-sorts are bracketed separately.  Prints ONE JSON line.  Inputs are generated
-on the host and are resident in HBM before the timed region starts.
+Each timed step is bracketed by HIP events on the library's stream: a step
+without a sort zeroes the moment grids (one fill) and replays the fused
+gather/push/deposit graph; a step at the sort cadence replays one graph that
+sorts, zeroes and steps (PL_SORT_FIRST).  Prints ONE JSON line.  Inputs are
+generated on the host and are resident in HBM before the timed region starts.
 
 Beside the headline, in the same line: the clumped 256^3 box and the batched
 workload (each with its own roofline), the Lagrangian spectral update on the
@@ -82,25 +83,32 @@ def src_digest():
 
 def timed_loop(run, steps, every, graph, torch, B):
     """`steps` steps with a sort every `every` steps (0: never); returns
-    (loop ms, per-launch kernel ms list, per-sort ms list)."""
+    (loop ms, per-launch kernel ms of the steps without a sort, per-step ms
+    of the steps with one).  With graphs, a sorting step is one recorded
+    sequence (PL_SORT_FIRST: sort, zeroing, step); the other steps zero the
+    moments with one fill and replay the step alone."""
     ev = lambda: torch.cuda.Event(enable_timing=True)
     flags = B.PL_FUSE_DEPOSIT | (B.PL_GRAPH if graph else 0)
     kpairs, spairs = [], []
     t0, t1 = ev(), ev()
     t0.record(run.stream)
     for s in range(steps):
+        a, b = ev(), ev()
         if every and s % every == 0:
-            a, b = ev(), ev()
             a.record(run.stream)
-            run.sort()
+            if graph:
+                run.step(flags=flags | B.PL_SORT_FIRST | B.PL_ZERO_FIRST)
+            else:
+                run.sort()
+                run.step(flags=flags | B.PL_ZERO_FIRST)
             b.record(run.stream)
             spairs.append((a, b))
-        run.zero_moments()
-        a, b = ev(), ev()
-        a.record(run.stream)
-        run.step(flags=flags)
-        b.record(run.stream)
-        kpairs.append((a, b))
+        else:
+            run.zero_moments()
+            a.record(run.stream)
+            run.step(flags=flags)
+            b.record(run.stream)
+            kpairs.append((a, b))
     t1.record(run.stream)
     t1.synchronize()
     st = run.sync()
@@ -118,8 +126,10 @@ def time_path(run, steps, warmup, reps, every, graph, torch, B):
         loops.append(ms / steps)
         kern.extend(k)
         sorts.extend(s)
+    kms = sum(kern) / len(kern)
+    # a sorting step's time beyond a plain step's: the sort (and the zeroing fill)
     return {"ms_per_step": statistics.median(loops), "ms_min": min(loops), "ms_max": max(loops),
-            "kernel_ms": sum(kern) / len(kern), "sort_ms": (sum(sorts) / len(sorts)) if sorts else 0.0}
+            "kernel_ms": kms, "sort_ms": (sum(sorts) / len(sorts) - kms) if sorts else 0.0}
 
 
 def touched_cells(x, n):
@@ -169,7 +179,6 @@ def time_workload(wl, cfg, steps, every, torch, B, driver):
     library's stream, one call per kind)."""
     run = driver.Run(wl, **cfg)
     try:
-        run.sort()
         run.sync()
         total = sum(it.particles.n for it in wl.items)
         timed_loop(run, 2, every, True, torch, B)
@@ -191,9 +200,10 @@ def time_workload(wl, cfg, steps, every, torch, B, driver):
         if run.sync() != B.PL_OK:
             raise RuntimeError("device reported an error")
         charged_ms = sum(a.elapsed_time(b) for a, b in pairs) / len(pairs)
+        kms = sum(kern) / len(kern)
         return {"value": total * steps / (ms * 1e-3), "unit": "particle-updates/s", "particles": total,
-                "ms_per_step": ms / steps, "kernel_ms": sum(kern) / len(kern),
-                "sort_ms": (sum(sorts) / len(sorts)) if sorts else 0.0, "sort_every": every, "steps": steps,
+                "ms_per_step": ms / steps, "kernel_ms": kms,
+                "sort_ms": (sum(sorts) / len(sorts) - kms) if sorts else 0.0, "sort_every": every, "steps": steps,
                 "charged_kernel_ms": charged_ms, "run_kernel_launches": stats[4], "tiled_fallback_groups": stats[5]}
     finally:
         run.close()
@@ -206,10 +216,11 @@ def extra_workloads(head_cfg, torch, B, driver, inputs):
     with the headline's kernel configuration, 20 steps each, each with its
     roofline: algorithmic bytes of the charged run kernel's launch over its
     time, and of the whole step (sort amortised) over the step time."""
+    from paper_2602_23434_amd import benchcfg as BC
     out = {}
-    cfg = {k: v for k, v in head_cfg.items() if k != "sort_every"}
-    for name, make, every, chans in (("clumped_256", inputs.clumped_box, 4, cfg.get("channels")),
-                                     ("batched_192", inputs.batched, head_cfg["sort_every"], None)):
+    bcfg = BC.batched_cfg()
+    for name, make, every, wcfg in (("clumped_256", inputs.clumped_box, 4, BC.run_kwargs(head_cfg)),
+                                    ("batched_192", inputs.batched, bcfg["sort_every"], BC.run_kwargs(bcfg))):
         t0 = time.perf_counter()
         wl = make()
         cells = [touched_cells(it.particles.x, wl.boxes[it.box].n) for it in wl.items]
@@ -222,9 +233,8 @@ def extra_workloads(head_cfg, torch, B, driver, inputs):
             per_box[bidx] = touched_cells(np.concatenate(xs, axis=1), wl.boxes[bidx].n) if len(xs) > 1 \
                 else per_box[bidx]
         log(f"[bench] {name}: inputs in {time.perf_counter() - t0:.1f} s")
-        wcfg = dict(cfg)
-        wcfg["channels"] = chans
         r = time_workload(wl, wcfg, 20, every, torch, B, driver)
+        r["config"] = {"tile": list(wcfg["tile"]), "sort_key": wcfg["key_mode"]}
         step_bytes, charged_bytes = workload_bytes(wl, per_box)
         npart = sum(it.particles.n for it in wl.items)
         sort_bytes = 132 * npart / every
@@ -415,8 +425,6 @@ def main():
     for name, cfg, ev_every, reps in paths:
         log(f"[bench] path {name}: setup")
         run = driver.Run(wl, **cfg)
-        if cfg["algo"] != B.PL_ALGO_PLAIN:
-            run.sort()
         run.sync()
         log(f"[bench] path {name}: {args.warmup} warmup + {reps} x {args.steps} timed steps, sort every {ev_every}")
         r = time_path(run, args.steps, args.warmup, reps, ev_every, not args.eager, torch, B)

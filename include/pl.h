@@ -123,6 +123,9 @@ typedef int pl_status;
 #define PL_ZERO_FIRST    (1u << 1)  /* zero the items' moment grids before depositing */
 #define PL_GRAPH         (1u << 2)  /* record the call's launches once as a hipGraph, replay afterwards */
 #define PL_SUMS          (1u << 3)  /* accumulate particle-side conservation sums (see pl_part_sums) */
+#define PL_SORT_FIRST    (1u << 4)  /* gather_push: sort every item first, exactly as pl_part_sort (tiled
+                                       and run-based algorithms); with PL_GRAPH the sort's launches are
+                                       recorded in the same graph as the zeroing and the step */
 
 typedef struct pl_ctx pl_ctx;
 
@@ -255,7 +258,10 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d);
  *   PL_SUMS          accumulate per-item particle-side sums (pl_part_sums);
  *   PL_GRAPH         record the launches as a hipGraph keyed by the call's
  *                    arguments and replay it on later identical calls
- *                    (the stream must not be the null stream).
+ *                    (the stream must not be the null stream);
+ *   PL_SORT_FIRST    sort every item first (pl_part_sort's result, cur
+ *                    flipped), then zero and step: with PL_GRAPH the whole
+ *                    sequence is one graph, a separate one per buffer set.
  * Items must not share particle arrays; items sharing a moment grid add into
  * it.
  */

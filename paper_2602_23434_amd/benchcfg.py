@@ -24,14 +24,14 @@ F64_RUNS = dict(prec=B.PL_F64, algo=B.PL_ALGO_RUNS, key_mode=B.PL_KEY_TILE_RUN, 
 SORT_EVERY = 8
 
 
-def _tuned(cfg, prec):
+def _tuned(cfg, prec, batched=False):
     """cfg with the autotuner's choice (tune_mi355x_*.txt next to this
     module, written by `python -m paper_2602_23434_amd.tune`) applied:
     algorithm, sort key, tile, block and sort cadence."""
     import os
 
     from . import tune
-    path = tune.tune_file(prec)
+    path = tune.tune_file(prec, batched)
     out = dict(cfg)
     out["sort_every"] = SORT_EVERY
     if not os.path.exists(path):
@@ -48,6 +48,22 @@ def _tuned(cfg, prec):
 def headline():
     """The float32 configuration the benchmark times (tuned when a tune file exists)."""
     return _tuned(F32_RUNS, B.PL_F32_OFFSET)
+
+
+def batched_cfg():
+    """The float32 configuration of the batched workload: the autotuner's
+    choice on that workload when its tune file exists, else the headline's;
+    every channel each species kind deposits."""
+    import os
+
+    from . import tune
+    if os.path.exists(tune.tune_file(B.PL_F32_OFFSET, batched=True)):
+        cfg = _tuned(F32_RUNS, B.PL_F32_OFFSET, batched=True)
+    else:
+        cfg = headline()
+    cfg = dict(cfg)
+    cfg["channels"] = None
+    return cfg
 
 
 def f64_sorted():

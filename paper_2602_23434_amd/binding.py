@@ -27,7 +27,7 @@ PL_RUNS_SPLIT_UNITS = 1024
 def runs_len(n, ntiles):
     """PL_RUNS_LEN: entries of the run table of n particles over ntiles tiles."""
     return n + 3 * ntiles + 2 * PL_RUNS_SPLIT_UNITS + 1
-PL_FUSE_DEPOSIT, PL_ZERO_FIRST, PL_GRAPH, PL_SUMS = 1, 2, 4, 8
+PL_FUSE_DEPOSIT, PL_ZERO_FIRST, PL_GRAPH, PL_SUMS, PL_SORT_FIRST = 1, 2, 4, 8, 16
 
 EXPORTS = ["pl_part_init", "pl_part_gather_push", "pl_part_deposit", "pl_part_sort", "pl_part_pack",
            "pl_part_unpack", "pl_part_sums", "pl_part_sync", "pl_part_set_stream", "pl_part_stats",

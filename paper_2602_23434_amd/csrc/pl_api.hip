@@ -332,39 +332,76 @@ uint64_t fnv1a(const void *p, size_t n, uint64_t h)
     return h;
 }
 
-pl_status run_call(Ctx *c, const pl_item *items, int nitems, double dt, uint32_t flags, Mode mode)
+pl_status sort_args(const Ctx *c, const pl_item &it, SortArgs &a);
+
+// One gather_push or deposit call: validate, optionally sort first, build the
+// item table, then queue the launches directly or through a recorded graph.
+pl_status run_call(Ctx *c, pl_item *items, int nitems, double dt, uint32_t flags, Mode mode)
 {
     const bool push = mode == MODE_STEP;
     const bool deposit = mode == MODE_DEPOSIT || (flags & PL_FUSE_DEPOSIT);
+    const bool sort_first = (flags & PL_SORT_FIRST) != 0;
+    if (!items || nitems < 1 || nitems > c->d.max_items) return PL_EINVAL;
+    // with PL_SORT_FIRST the step sees every item after its sort: the other set
+    std::vector<SortArgs> sargs;
+    std::vector<pl_item> sorted;
+    const pl_item *step_items = items;
+    if (sort_first) {
+        if (!push || c->d.algo == PL_ALGO_PLAIN) return PL_EINVAL;
+        sargs.resize(nitems);
+        sorted.assign(items, items + nitems);
+        for (int i = 0; i < nitems; ++i) {
+            pl_status st = sort_args(c, items[i], sargs[i]);
+            if (st != PL_OK) return st;
+            sorted[i].p.cur = 1 - sorted[i].p.cur;
+        }
+        step_items = sorted.data();
+    }
     std::vector<ItemDesc> host;
     int total = 0;
-    pl_status st = build_table(c, items, nitems, dt, mode, deposit, host, total);
+    pl_status st = build_table(c, step_items, nitems, dt, mode, deposit, host, total);
     if (st != PL_OK) return st;
-    if (push) {
-        // this step rewrites p.fp in the items' current order
+
+    auto enqueue = [&](const ItemDesc *table) -> pl_status {
+        for (const SortArgs &a : sargs)
+            if (launch_sort(c, a) != hipSuccess) return PL_EHIP;
+        return enqueue_step(c, table, host, total, flags, push, deposit);
+    };
+    // host bookkeeping once the launches are queued: the sort flipped the sets,
+    // and this step rewrites p.fp in the items' (new) order
+    auto done = [&]() {
         for (int i = 0; i < nitems; ++i) {
-            auto it = std::find(c->fp_stale.begin(), c->fp_stale.end(), (const void *)items[i].p.fp[0]);
-            if (it != c->fp_stale.end()) c->fp_stale.erase(it);
+            if (sort_first) {
+                items[i].p.cur = 1 - items[i].p.cur;
+                c->stats[3]++;
+            }
+            if (push) {
+                auto it = std::find(c->fp_stale.begin(), c->fp_stale.end(), (const void *)items[i].p.fp[0]);
+                if (it != c->fp_stale.end()) c->fp_stale.erase(it);
+            }
         }
-    }
+        return PL_OK;
+    };
 
     if (!(flags & PL_GRAPH)) {
         st = upload_table(c, host, c->table);
         if (st != PL_OK) return st;
-        return enqueue_step(c, c->table, host, total, flags, push, deposit);
+        st = enqueue(c->table);
+        return st == PL_OK ? done() : st;
     }
 
     if (!c->stream) return PL_EINVAL;   // the null stream cannot be captured
     uint64_t key = fnv1a(host.data(), host.size() * sizeof(ItemDesc), 1469598103934665603ull);
     uint32_t tag[2] = {flags, (uint32_t)mode};
     key = fnv1a(tag, sizeof(tag), key);
+    if (!sargs.empty()) key = fnv1a(sargs.data(), sargs.size() * sizeof(SortArgs), key);
     c->use_clock++;
     for (auto &g : c->graphs) {
         if (g.valid && g.key == key && g.nitems == (int)host.size()) {
             g.last_use = c->use_clock;
             PL_TRY_HIP(hipGraphLaunch(g.exec, c->stream));
             c->stats[1]++;
-            return PL_OK;
+            return done();
         }
     }
     // record a new graph in the least recently used slot
@@ -380,7 +417,7 @@ pl_status run_call(Ctx *c, const pl_item *items, int nitems, double dt, uint32_t
     PL_TRY_HIP(hipStreamSynchronize(c->stream));
     PL_TRY_HIP(hipMemcpy(slot->table, host.data(), host.size() * sizeof(ItemDesc), hipMemcpyHostToDevice));
     PL_TRY_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    pl_status est = enqueue_step(c, slot->table, host, total, flags, push, deposit);
+    pl_status est = enqueue(slot->table);
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamEndCapture(c->stream, &graph);
     if (est != PL_OK) {
@@ -402,7 +439,7 @@ pl_status run_call(Ctx *c, const pl_item *items, int nitems, double dt, uint32_t
     c->stats[2]++;
     PL_TRY_HIP(hipGraphLaunch(exec, c->stream));
     c->stats[1]++;
-    return PL_OK;
+    return done();
 }
 
 }  // namespace
@@ -513,7 +550,7 @@ pl_status pl_part_gather_push(pl_ctx *ctx, pl_item *items, int nitems, double dt
 {
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
     if (!c || !isfinite(dt) || dt == 0.0) return PL_EINVAL;
-    if (flags & ~(PL_FUSE_DEPOSIT | PL_ZERO_FIRST | PL_GRAPH | PL_SUMS)) return PL_EINVAL;
+    if (flags & ~(PL_FUSE_DEPOSIT | PL_ZERO_FIRST | PL_GRAPH | PL_SUMS | PL_SORT_FIRST)) return PL_EINVAL;
     return run_call(c, items, nitems, dt, flags, MODE_STEP);
 }
 
@@ -522,7 +559,7 @@ pl_status pl_part_deposit(pl_ctx *ctx, const pl_item *items, int nitems, uint32_
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
     if (!c) return PL_EINVAL;
     if (flags & ~(PL_ZERO_FIRST | PL_GRAPH)) return PL_EINVAL;
-    return run_call(c, items, nitems, 0.0, flags, MODE_DEPOSIT);
+    return run_call(c, const_cast<pl_item *>(items), nitems, 0.0, flags, MODE_DEPOSIT);
 }
 
 }  // extern "C"

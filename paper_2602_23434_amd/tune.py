@@ -4,11 +4,14 @@ order (run order or tile+cell order) and sort cadence of the run-based kernel
 candidate).
 
     python -m paper_2602_23434_amd.tune [--f64] [--n 128 --ppc 8 --steps 32] [--out FILE]
+    python -m paper_2602_23434_amd.tune --batched [--steps 20]
 
 For every candidate it builds a context on a synthetic turbulent box of the
-requested size and times `steps` fused steps with the sort repeated at the
-candidate cadence, so the sort's cost is amortised into the per-step time
-exactly as in the benchmark.  The winner is written as "key value" lines:
+requested size (or, with --batched, on the full batched workload: a 192^3 box
+with charged, dust and tracer particles plus 16 boxes of 64^3) and times
+`steps` fused steps with the sort repeated at the candidate cadence (one
+graph sorts, zeroes and steps), so the sort's cost is amortised into the
+per-step time exactly as in the benchmark.  The winner is written as "key value" lines:
 pl_part_init reads block, runs_block and tile; the Python side reads algo,
 key and sort_every.  Without --out the file is the package's tune file for
 the precision (tune_mi355x_f32.txt / tune_mi355x_f64.txt).
@@ -33,22 +36,23 @@ CADENCES = [8, 16, 32]
 CHANNELS = ["rho", "J0", "J1", "J2", "F0", "F1", "F2"]
 
 
-def tune_file(prec):
+def tune_file(prec, batched=False):
+    if batched:
+        return os.path.join(HERE, "tune_mi355x_f32_batched.txt")
     return os.path.join(HERE, "tune_mi355x_f32.txt" if prec == B.PL_F32_OFFSET else "tune_mi355x_f64.txt")
 
 
-def time_candidate(wl, prec, algo, tile, block, key, every, steps, torch, reps=3):
+def time_candidate(wl, prec, algo, tile, block, key, every, steps, torch, reps=3, channels=CHANNELS):
     """Median over `reps` timed loops of `steps` steps (the sort repeated at
     the candidate's cadence), in ms per step; None when unsupported."""
     try:
-        run = driver.Run(wl, prec=prec, algo=algo, tile=tile, block=block, key_mode=key, channels=CHANNELS,
+        run = driver.Run(wl, prec=prec, algo=algo, tile=tile, block=block, key_mode=key, channels=channels,
                          eng=False)
     except B.PLError:
         return None
     try:
         flags = B.PL_FUSE_DEPOSIT | B.PL_ZERO_FIRST | B.PL_GRAPH
-        run.sort()
-        run.step(flags=flags)
+        run.step(flags=flags | B.PL_SORT_FIRST)
         run.sync()
         times = []
         for _ in range(reps):
@@ -56,9 +60,7 @@ def time_candidate(wl, prec, algo, tile, block, key, every, steps, torch, reps=3
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(run.stream)
             for s in range(steps):
-                if s % every == 0:
-                    run.sort()
-                run.step(flags=flags)
+                run.step(flags=flags | (B.PL_SORT_FIRST if s % every == 0 else 0))
             e1.record(run.stream)
             e1.synchronize()
             times.append(e0.elapsed_time(e1) / steps)
@@ -90,16 +92,23 @@ def candidates(n, prec):
         yield B.PL_ALGO_TILED, tile, 512, B.PL_KEY_TILE_RANK, every
 
 
-def tune(n=128, ppc=8, steps=32, prec=B.PL_F32_OFFSET, log=print):
+def tune(n=128, ppc=8, steps=32, prec=B.PL_F32_OFFSET, log=print, batched=False):
     import torch
-    wl = inputs.turbulent_box(n=n, npart=ppc * n ** 3, steps=steps)
+    if batched:
+        wl = inputs.batched(steps=steps)
+        n = 64                  # every tile must divide every box (192 and 64)
+        channels = None
+    else:
+        wl = inputs.turbulent_box(n=n, npart=ppc * n ** 3, steps=steps)
+        channels = CHANNELS
     best = None
     results = []
     # one untimed pass first, so the first candidate does not pay for clocks ramping up
     first = next(iter(candidates(n, prec)))
-    time_candidate(wl, prec, first[0], first[1], first[2], first[3], first[4], steps, torch, reps=1)
+    time_candidate(wl, prec, first[0], first[1], first[2], first[3], first[4], steps, torch, reps=1,
+                   channels=channels)
     for algo, tile, block, key, every in candidates(n, prec):
-        ms = time_candidate(wl, prec, algo, tile, block, key, every, steps, torch)
+        ms = time_candidate(wl, prec, algo, tile, block, key, every, steps, torch, channels=channels)
         results.append({"algo": algo, "tile": tile, "block": block, "key": key, "sort_every": every, "ms": ms})
         log(f"[tune] algo {algo} tile {tile} block {block} key {key} sort_every {every}: "
             f"{'unsupported' if ms is None else f'{ms:.3f} ms/step'}")
@@ -108,9 +117,9 @@ def tune(n=128, ppc=8, steps=32, prec=B.PL_F32_OFFSET, log=print):
     return best, results
 
 
-def write_cache(path, best, n, ppc):
+def write_cache(path, best, what):
     with open(path, "w") as fh:
-        fh.write(f"# autotuned on MI355X: turbulent {n}^3 box, {ppc} particles per cell\n")
+        fh.write(f"# autotuned on MI355X: {what}\n")
         fh.write(f"algo {best['algo']}\n")
         fh.write(f"key {best['key']}\n")
         if best["algo"] == B.PL_ALGO_RUNS:
@@ -141,11 +150,15 @@ def main():
     ap.add_argument("--ppc", type=int, default=8)
     ap.add_argument("--steps", type=int, default=32)
     ap.add_argument("--f64", action="store_true")
+    ap.add_argument("--batched", action="store_true", help="tune on the batched workload (float32 form)")
     a = ap.parse_args()
     prec = B.PL_F64 if a.f64 else B.PL_F32_OFFSET
     t0 = time.perf_counter()
-    best, results = tune(a.n, a.ppc, a.steps, prec, log=lambda m: print(m, file=sys.stderr, flush=True))
-    write_cache(a.out or tune_file(prec), best, a.n, a.ppc)
+    best, results = tune(a.n, a.ppc, a.steps, prec, log=lambda m: print(m, file=sys.stderr, flush=True),
+                         batched=a.batched)
+    what = ("batched workload: 192^3 box (charged, dust, tracers) + 16 boxes of 64^3" if a.batched
+            else f"turbulent {a.n}^3 box, {a.ppc} particles per cell")
+    write_cache(a.out or tune_file(prec, a.batched), best, what)
     print(json.dumps({"best": best, "seconds": time.perf_counter() - t0}))
 
 

@@ -59,9 +59,8 @@ def _bench_run(driver, B, wl, cfg, every):
     from paper_2602_23434_amd import benchcfg as BC
     run = driver.Run(wl, **BC.run_kwargs(cfg))
     for s in range(wl.steps):
-        if s % every == 0:
-            run.sort()
-        run.step(flags=BC.STEP_FLAGS)
+        # the benchmark's sequence: a sorting step is one graph (sort, zero, step)
+        run.step(flags=BC.STEP_FLAGS | (B.PL_SORT_FIRST if s % every == 0 else 0))
     assert run.sync() == B.PL_OK
     return run
 

@@ -41,9 +41,8 @@ def _run(driver, B, wl, cfg, steps, every):
     from paper_2602_23434_amd import benchcfg as BC
     run = driver.Run(wl, **BC.run_kwargs(cfg))
     for s in range(steps):
-        if s % every == 0:
-            run.sort()
-        fl = BC.STEP_FLAGS | (B.PL_SUMS if s == steps - 1 else 0)
+        # the benchmark's sequence: a sorting step is one graph (sort, zero, step)
+        fl = BC.STEP_FLAGS | (B.PL_SUMS if s == steps - 1 else 0) | (B.PL_SORT_FIRST if s % every == 0 else 0)
         run.step(flags=fl)
     assert run.sync() == B.PL_OK
     st = B.pl_part_stats(run.ctx)
@@ -102,8 +101,7 @@ def test_batched_fullsize(mods):
     from paper_2602_23434_amd import benchcfg as BC
     say("[full] batched: 192^3 box (charged, dust, tracers) + 16 boxes of 64^3, 20 steps, f32 runs")
     wl = inputs.batched()
-    cfg = dict(BC.headline())
-    cfg["channels"] = None
+    cfg = BC.batched_cfg()
     run = _run(driver, B, wl, cfg, wl.steps, cfg["sort_every"])
     sums = run.sums()
     for i in range(len(wl.items)):
