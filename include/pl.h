@@ -92,8 +92,9 @@ typedef int pl_status;
                               float64 particles): each batch particle gathers its fields from the
                               LDS field tile, and the batch's deposits into a stencil point are
                               summed in registers before one LDS atomic per channel (3D/2D,
-                              TSC/CIC, charged and dust species; tracers and deposit-only calls
-                              run the PL_ALGO_TILED kernel).
+                              TSC/CIC; charged, dust and, from the same field tile, tracer
+                              species; push-only and deposit-only calls run the PL_ALGO_TILED
+                              kernel).
                               Needs pl_part_sort with PL_KEY_TILE_CELL or PL_KEY_TILE_RUN,
                               which writes p.runs */
 
@@ -248,10 +249,10 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d);
  * velocity frozen over the step.  With PL_FUSE_DEPOSIT every channel is
  * deposited at x^{n+1}, J with u^{n+1/2}, F = m w (u^{n+1/2} - u^{n-1/2})/dt.
  * When p.fp is given it receives F of each particle, in the particle order of
- * this call.  Items of one species kind share one persistent launch whose
- * blocks claim (item, tile) work units from one counter; a call holding
- * several kinds makes one launch per kind (the run-based kernel for charged
- * and dust items, the tiled kernel for tracers).
+ * this call.  With PL_ALGO_RUNS and PL_FUSE_DEPOSIT every item of the call,
+ * of every species kind, goes to one persistent launch whose blocks claim
+ * (item, tile piece) work units from one counter and run each with its
+ * item's kind; otherwise the items of each kind share one launch.
  *   PL_FUSE_DEPOSIT  deposit the items' non-NULL moment channels at x^{n+1}
  *                    in the same pass (added to the grids' contents);
  *   PL_ZERO_FIRST    zero those channels first;
@@ -429,9 +430,11 @@ pl_status pl_part_set_stream(pl_ctx *ctx, void *stream);
  * launch groups that took the tiled kernel because the run-based kernel's
  * LDS footprint exceeds the device's, out[6] launches of a run-based kernel
  * compiled for a fixed tile shape and channel set, out[7] the variant of the
- * last run-based launch: ts | chs << 4 | hf << 8, with ts the fixed tile
+ * last run-based launch: ts | chs << 4 | hf << 8 | mixed << 12, with mixed = 1
+ * when the launch took items of several kinds (or tracers), ts the fixed tile
  * (1: 8x8x8, 2: 8x8x4, 0: taken at run time), chs the fixed channel set
- * (1: rho J F of charged particles, 2: rho F of dust, 0: taken at run time)
+ * (1: rho J F of charged particles, 2: rho F of dust, 0: taken at run time;
+ * a mixed launch reports its charged items' set)
  * and hf the field halo in cells (1 or 2). */
 #define PL_NSTATS 8
 pl_status pl_part_stats(pl_ctx *ctx, int64_t *out, int n);

@@ -236,7 +236,8 @@ def pl_part_stats(ctx):
 
 
 def runs_variant(stats):
-    """(ts, chs, hf) of the last run-based launch from pl_part_stats' out[7]."""
+    """(ts, chs, hf) of the last run-based launch from pl_part_stats' out[7]
+    (bit 12, a launch over several species kinds, is not part of it)."""
     v = int(stats[7])
     return v & 15, (v >> 4) & 15, (v >> 8) & 15
 

@@ -718,181 +718,217 @@ __host__ __device__ inline size_t runs_lds_bytes(int Lf, int Ld, int nslot, int 
 // on reads in flight.
 constexpr int kRunsThreads = 512;
 
-// HF: field halo width (1 or 2) fixed at compile time, or 0 to take it from
-// the launch flags; TS and HF fixed make every LDS stencil offset an
-// immediate.
+// Gas velocity at a position of the Runge-Kutta scheme: from the LDS field
+// records when the stencil lies in the tile's field tile, else from the grid.
+template <int PREC, int SHAPE, int DIM>
+__device__ __forceinline__ void tracer_velocity(const UnitC<PREC> &U, const RunGeo &G,
+                                                const typename RealOf<PREC>::T *lds_f, const Pos<PREC, DIM> &q,
+                                                typename RealOf<PREC>::T k[3])
+{
+    using R = typename RealOf<PREC>::T;
+    R dm[3] = {(R)q.d[0], (R)q.d[1], (R)q.d[2]};
+    R sx[3], sy[3], sz[3];
+    stencil_weights<PREC, SHAPE, DIM>(dm, sx, sy, sz);
+    int fb = 0;
+    if (field_base<DIM>(G, U.n, q.c, fb)) gather_rec<PREC, DIM, PL_TRACER>(G, lds_f, fb, sx, sy, sz, k);
+    else gather<PREC, DIM, 3>(U, nullptr, 0, false, 0, 0, 0, q.c, sx, sy, sz, k);
+}
+
+// One passive tracer on the gas velocity frozen over the step (Eq. 1):
+// Heun's two-stage scheme, or the three-stage SSP scheme of Shu and Osher,
+// x + dt (k1 + k2 + 4 k3) / 6 with k1 = v(x), k2 = v(x + dt k1),
+// k3 = v(x + dt (k1 + k2) / 4); the stored velocity is the step's mean.
+// The same terms in the same order as the tiled kernel's tracer path.
+template <int PREC, int SHAPE, int DIM>
+__device__ __forceinline__ void tracer_particle(const UnitC<PREC> &U, const RunGeo &G,
+                                                const typename RealOf<PREC>::T *lds_f, int p, int &err)
+{
+    using R = typename RealOf<PREC>::T;
+    Pos<PREC, DIM> pos;
+    pos.load(U, p, err);
+    R k1[3], k2[3], v[3];
+    tracer_velocity<PREC, SHAPE, DIM>(U, G, lds_f, pos, k1);
+    // velocity of the stage at x + dt * s (s in cells per unit time)
+    auto stage = [&](const R sv[3], R k[3]) {
+        Pos<PREC, DIM> mid = pos;
+        R dd[3] = {R(0), R(0), R(0)};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) dd[a] = sv[a] * U.dtdx[a];
+        mid.advance(dd, U, err);
+        tracer_velocity<PREC, SHAPE, DIM>(U, G, lds_f, mid, k);
+    };
+    stage(k1, k2);
+    if (U.rk == 3) {
+        R hq[3], k3[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) hq[a] = R(0.25) * (k1[a] + k2[a]);
+        stage(hq, k3);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[a] = (k1[a] + k2[a] + R(4) * k3[a]) / R(6);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[a] = R(0.5) * (k1[a] + k2[a]);
+    }
+    R disp[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) disp[a] = v[a] * U.dtdx[a];
+    pos.advance(disp, U, err);
+    pos.store(U, p);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) U.u[a][p] = v[a];
+}
+
+// One work unit of the run kernel (a piece of tile t of item I): stage the
+// tile's field records (and clear its deposit tile), advance the piece's
+// runs, and flush the deposits; passive tracers are advanced one particle at
+// a time from the same field records.  The next unit is claimed into ctl[0]
+// before the flush (pre = true).
 template <int PREC, int SHAPE, int DIM, int KIND, int HF, int TS, int CHS>
-__global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_runs(const ItemDesc *__restrict__ items, int nitems, int total_units,
-                                             unsigned *counter, int *errflags, unsigned flags, int lds_bytes)
+__device__ __forceinline__ void runs_unit(const ItemDesc &I, int t, int piece, int npieces, unsigned flags,
+                                          int lds_bytes, unsigned char *smem_raw, unsigned *counter, bool &pre,
+                                          int &err)
 {
     using R = typename RealOf<PREC>::T;
     using FR = FieldRec<PREC, KIND>;
     constexpr int NC = FR::NC, FS = FR::FS;
     constexpr int KR = PREC == PL_F32_OFFSET ? 4 : 2;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     int *ctl = reinterpret_cast<int *>(smem_raw + lds_bytes - 16);
     const bool do_sums = flags & SF_SUMS;
-    int err = 0;
+    RunGeo G;
+    G.T[0] = TS ? ts_dim(TS, 0) : I.tile[0];
+    G.T[1] = TS ? ts_dim(TS, 1) : I.tile[1];
+    G.T[2] = TS ? ts_dim(TS, 2) : I.tile[2];
+    {
+        int tx = t % I.ntile[0];
+        int ty = (t / I.ntile[0]) % I.ntile[1];
+        int tz = t / (I.ntile[0] * I.ntile[1]);
+        G.lo[0] = tx * G.T[0];
+        G.lo[1] = ty * G.T[1];
+        G.lo[2] = tz * G.T[2];
+    }
+    G.hf = HF ? HF : ((flags & SF_FHALO2) ? 2 : 1);
+    G.fx = G.T[0] + 2 * G.hf;
+    G.fxy = G.fx * (G.T[1] + 2 * G.hf);
+    G.Lf = G.fxy * (DIM >= 3 ? G.T[2] + 2 * G.hf : 1);
+    G.dx = G.T[0] + 4;
+    G.dxy = G.dx * (G.T[1] + 4);
+    G.Ld = G.dxy * (DIM >= 3 ? G.T[2] + 4 : 1);
+    const int pbeg = min(max(I.tile_start[t], 0), I.np);
+    const int pend = min(max(I.tile_start[t + 1], pbeg), I.np);
+    const int nruns = min(max(I.runs[I.np + t], 0), pend - pbeg);
+    const int r_lo = (int)((long long)nruns * piece / npieces);
+    const int r_hi = (int)((long long)nruns * (piece + 1) / npieces);
+    if (r_hi <= r_lo) return;        // uniform: the whole block skips an empty piece
 
-    bool pre = false;                      // uniform: ctl[0] already holds the next claim
-    for (;;) {
-        __syncthreads();
-        if (!pre && threadIdx.x == 0) ctl[0] = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        pre = false;
-        const int g = __builtin_amdgcn_readfirstlane(ctl[0]);
-        if ((unsigned)g >= (unsigned)total_units) break;
-        // item k of the launch owns units [unit_begin + k * kRunsSplit, + nunits + kRunsSplit)
-        int iti = 0;
-        while (iti + 1 < nitems && items[iti + 1].unit_begin + (iti + 1) * kRunsSplit <= g) ++iti;
-        const ItemDesc &I = items[iti];
-        const int ubeg = I.unit_begin + iti * kRunsSplit;
-        const int ucap = I.nunits + kRunsSplit;
-        const int local = g - ubeg;
-        const int nu = min(max(I.runs[runs_count_at(I.np, I.ntiles)], 0), I.nunits > 0 ? ucap : 0);
-        // the sort's tables must cover the item's particles: tile offsets from
-        // 0 to np and at least one unit when np > 0; otherwise the item was
-        // never sorted (or its count changed since): latch it, leave it alone
-        const bool stale = I.tile_start[0] != 0 || I.tile_start[I.ntiles] != I.np || (I.np > 0 && nu == 0);
-        if (stale || local >= nu) {
-            // the rest of this item's units are empty: move the counter past them
-            if (threadIdx.x == 0) {
-                atomicMax(counter, (unsigned)(ubeg + ucap));
-                if (stale) atomicOr(errflags, (int)ERR_UNSORTED);
-            }
-            continue;                                          // uniform
-        }
-        // the sort lists the units largest first: (tile, piece | npieces << 16)
-        const int32_t *unit = I.runs + runs_units_at(I.np, I.ntiles) + 2 * local;
-        const int t = unit[0];
-        const int piece = unit[1] & 0xffff, npieces = unit[1] >> 16;
-        if ((unsigned)t >= (unsigned)I.ntiles || npieces < 1 || piece >= npieces) continue;      // uniform
-        RunGeo G;
-        G.T[0] = TS ? ts_dim(TS, 0) : I.tile[0];
-        G.T[1] = TS ? ts_dim(TS, 1) : I.tile[1];
-        G.T[2] = TS ? ts_dim(TS, 2) : I.tile[2];
-        {
-            int tx = t % I.ntile[0];
-            int ty = (t / I.ntile[0]) % I.ntile[1];
-            int tz = t / (I.ntile[0] * I.ntile[1]);
-            G.lo[0] = tx * G.T[0];
-            G.lo[1] = ty * G.T[1];
-            G.lo[2] = tz * G.T[2];
-        }
-        G.hf = HF ? HF : ((flags & SF_FHALO2) ? 2 : 1);
-        G.fx = G.T[0] + 2 * G.hf;
-        G.fxy = G.fx * (G.T[1] + 2 * G.hf);
-        G.Lf = G.fxy * (DIM >= 3 ? G.T[2] + 2 * G.hf : 1);
-        G.dx = G.T[0] + 4;
-        G.dxy = G.dx * (G.T[1] + 4);
-        G.Ld = G.dxy * (DIM >= 3 ? G.T[2] + 4 : 1);
-        const int pbeg = min(max(I.tile_start[t], 0), I.np);
-        const int pend = min(max(I.tile_start[t + 1], pbeg), I.np);
-        const int nruns = min(max(I.runs[I.np + t], 0), pend - pbeg);
-        const int r_lo = (int)((long long)nruns * piece / npieces);
-        const int r_hi = (int)((long long)nruns * (piece + 1) / npieces);
-        if (r_hi <= r_lo) continue;        // uniform: the whole block skips an empty piece
+    UnitC<PREC> U;
+    load_unit<PREC>(I, U, G.Ld);
+    const int nslot = I.nslot;
+    size_t offs[6];
+    runs_lds_bytes<PREC, KIND>(G.Lf, G.Ld, nslot, G.hf, offs);
+    RunShared<PREC> S;
+    R *lds_f = reinterpret_cast<R *>(smem_raw + offs[0]);
+    S.lds_f = lds_f;
+    S.lds_d = reinterpret_cast<double *>(smem_raw + offs[1]);
+    S.gq = reinterpret_cast<int *>(smem_raw + offs[2]);
+    S.dq_c = reinterpret_cast<uint32_t *>(smem_raw + offs[3]);
+    S.dq_d = reinterpret_cast<R *>(smem_raw + offs[4]);
+    S.dq_mu = S.dq_d + 3 * RunsQ<PREC>::DQ;
+    S.ctl = ctl;
+    S.sums = reinterpret_cast<double *>(smem_raw + offs[5]);
 
-        UnitC<PREC> U;
-        load_unit<PREC>(I, U, G.Ld);
-        const int nslot = I.nslot;
-        size_t offs[6];
-        runs_lds_bytes<PREC, KIND>(G.Lf, G.Ld, nslot, G.hf, offs);
-        RunShared<PREC> S;
-        R *lds_f = reinterpret_cast<R *>(smem_raw + offs[0]);
-        S.lds_f = lds_f;
-        S.lds_d = reinterpret_cast<double *>(smem_raw + offs[1]);
-        S.gq = reinterpret_cast<int *>(smem_raw + offs[2]);
-        S.dq_c = reinterpret_cast<uint32_t *>(smem_raw + offs[3]);
-        S.dq_d = reinterpret_cast<R *>(smem_raw + offs[4]);
-        S.dq_mu = S.dq_d + 3 * RunsQ<PREC>::DQ;
-        S.ctl = ctl;
-        S.sums = reinterpret_cast<double *>(smem_raw + offs[5]);
-
-        // stage the field records (hf-cell halo) and clear the deposit tile.
-        // Float32 form: two-deep pipeline, a record's loads are issued before
-        // the previous record is stored, and the first loads overlap the
-        // clearing.
-        {
-            const int Ly = G.T[1] + 2 * G.hf;
-            auto rec_cell = [&](int e) -> long {
-                int lx = e % G.fx;
-                int ly = (e / G.fx) % Ly;
-                int lz = e / G.fxy;
-                int gx = wrap_any(G.lo[0] + lx - G.hf, U.n[0]);
-                int gy = DIM >= 2 ? wrap_any(G.lo[1] + ly - G.hf, U.n[1]) : 0;
-                int gz = DIM >= 3 ? wrap_any(G.lo[2] + lz - G.hf, U.n[2]) : 0;
-                return gx + (long)U.n[0] * (gy + (long)U.n[1] * gz);
-            };
-            auto rec_load = [&](int e, double (&v)[NC]) {
-                const long gc = rec_cell(e);
-#pragma unroll
-                for (int q = 0; q < NC; ++q) v[q] = U.gf[q][gc];
-            };
-            // one 16-byte LDS store per 16 bytes of record (conflict-free:
-            // consecutive threads write consecutive records)
-            auto rec_store = [&](int e, const double (&v)[NC]) {
-                if constexpr (FR::PLANES) {
-                    *reinterpret_cast<float4 *>(lds_f + FR::at(e, 0, G.Lf)) =
-                        make_float4((R)v[0], (R)v[1], (R)v[2], 0.0f);
-                    *reinterpret_cast<float4 *>(lds_f + FR::at(e, 3, G.Lf)) =
-                        make_float4((R)v[3], (R)v[4], (R)v[5], 0.0f);
-                } else {
-                    R w[FS];
-#pragma unroll
-                    for (int q = 0; q < FS; ++q) w[q] = q < NC ? (R)v[q] : R(0);
-                    if constexpr (PREC == PL_F32_OFFSET) {
-                        *reinterpret_cast<float4 *>(lds_f + FS * e) = make_float4(w[0], w[1], w[2], w[3]);
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < FS / 2; ++k)
-                            *reinterpret_cast<double2 *>(lds_f + FS * e + 2 * k) = make_double2(w[2 * k], w[2 * k + 1]);
-                    }
-                }
-            };
-            if constexpr (PREC == PL_F32_OFFSET) {
-                double cur[NC];
-                int e = threadIdx.x;
-                if (e < G.Lf) rec_load(e, cur);
-                for (int k = threadIdx.x; k < G.Ld * nslot; k += blockDim.x) S.lds_d[k] = 0.0;
-                for (; e < G.Lf; e += blockDim.x) {
-                    double nxt[NC];
-                    const int en = e + (int)blockDim.x;
-                    if (en < G.Lf) rec_load(en, nxt);
-                    rec_store(e, cur);
-#pragma unroll
-                    for (int q = 0; q < NC; ++q) cur[q] = nxt[q];
-                }
-            } else {
-                // float64 records: one at a time (the pipeline's registers spill there)
-                for (int e = threadIdx.x; e < G.Lf; e += blockDim.x) {
-                    double v[NC];
-                    rec_load(e, v);
-                    rec_store(e, v);
-                }
-                for (int k = threadIdx.x; k < G.Ld * nslot; k += blockDim.x) S.lds_d[k] = 0.0;
-            }
-            if (threadIdx.x == 0) {
-                ctl[1] = 0;
-                ctl[2] = 0;
-            }
-            if (threadIdx.x < 8) S.sums[threadIdx.x] = 0.0;
-            __syncthreads();
-        }
-
-        // this thread's runs r = r_lo + tid, + blockDim, ..., each cut into
-        // batches of KR; the next batch is fetched before the current one runs.
-        // A long piece is taken in segments of 4 * blockDim runs with the LDS
-        // queues drained between segments when half full; every piece ends
-        // with a drain.  Segment count, drain decisions and barriers are
-        // uniform across the block.  Pieces of one tile on several CUs meet
-        // only in the global atomics of the flush.
-        const gptr<const int32_t> runs = (gptr<const int32_t>)(I.runs + pbeg);
-        auto run_span = [&](int r, int &rs, int &rl) {
-            const int e = runs[r];
-            rs = min(max(e >> 2, pbeg), pend - 1);
-            rl = min((e & 3) + 1, pend - rs);
+    // stage the field records (hf-cell halo) and clear the deposit tile.
+    // Float32 form: two-deep pipeline, a record's loads are issued before
+    // the previous record is stored, and the first loads overlap the
+    // clearing.
+    {
+        const int Ly = G.T[1] + 2 * G.hf;
+        auto rec_cell = [&](int e) -> long {
+            int lx = e % G.fx;
+            int ly = (e / G.fx) % Ly;
+            int lz = e / G.fxy;
+            int gx = wrap_any(G.lo[0] + lx - G.hf, U.n[0]);
+            int gy = DIM >= 2 ? wrap_any(G.lo[1] + ly - G.hf, U.n[1]) : 0;
+            int gz = DIM >= 3 ? wrap_any(G.lo[2] + lz - G.hf, U.n[2]) : 0;
+            return gx + (long)U.n[0] * (gy + (long)U.n[1] * gz);
         };
+        auto rec_load = [&](int e, double (&v)[NC]) {
+            const long gc = rec_cell(e);
+#pragma unroll
+            for (int q = 0; q < NC; ++q) v[q] = U.gf[q][gc];
+        };
+        // one 16-byte LDS store per 16 bytes of record (conflict-free:
+        // consecutive threads write consecutive records)
+        auto rec_store = [&](int e, const double (&v)[NC]) {
+            if constexpr (FR::PLANES) {
+                *reinterpret_cast<float4 *>(lds_f + FR::at(e, 0, G.Lf)) =
+                    make_float4((R)v[0], (R)v[1], (R)v[2], 0.0f);
+                *reinterpret_cast<float4 *>(lds_f + FR::at(e, 3, G.Lf)) =
+                    make_float4((R)v[3], (R)v[4], (R)v[5], 0.0f);
+            } else {
+                R w[FS];
+#pragma unroll
+                for (int q = 0; q < FS; ++q) w[q] = q < NC ? (R)v[q] : R(0);
+                if constexpr (PREC == PL_F32_OFFSET) {
+                    *reinterpret_cast<float4 *>(lds_f + FS * e) = make_float4(w[0], w[1], w[2], w[3]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < FS / 2; ++k)
+                        *reinterpret_cast<double2 *>(lds_f + FS * e + 2 * k) = make_double2(w[2 * k], w[2 * k + 1]);
+                }
+            }
+        };
+        if constexpr (PREC == PL_F32_OFFSET) {
+            double cur[NC];
+            int e = threadIdx.x;
+            if (e < G.Lf) rec_load(e, cur);
+            for (int k = threadIdx.x; k < G.Ld * nslot; k += blockDim.x) S.lds_d[k] = 0.0;
+            for (; e < G.Lf; e += blockDim.x) {
+                double nxt[NC];
+                const int en = e + (int)blockDim.x;
+                if (en < G.Lf) rec_load(en, nxt);
+                rec_store(e, cur);
+#pragma unroll
+                for (int q = 0; q < NC; ++q) cur[q] = nxt[q];
+            }
+        } else {
+            // float64 records: one at a time (the pipeline's registers spill there)
+            for (int e = threadIdx.x; e < G.Lf; e += blockDim.x) {
+                double v[NC];
+                rec_load(e, v);
+                rec_store(e, v);
+            }
+            for (int k = threadIdx.x; k < G.Ld * nslot; k += blockDim.x) S.lds_d[k] = 0.0;
+        }
+        if (threadIdx.x == 0) {
+            ctl[1] = 0;
+            ctl[2] = 0;
+        }
+        if (threadIdx.x < 8) S.sums[threadIdx.x] = 0.0;
+        __syncthreads();
+    }
+
+    // this thread's runs r = r_lo + tid, + blockDim, ..., each cut into
+    // batches of KR; the next batch is fetched before the current one runs.
+    // A long piece is taken in segments of 4 * blockDim runs with the LDS
+    // queues drained between segments when half full; every piece ends
+    // with a drain.  Segment count, drain decisions and barriers are
+    // uniform across the block.  Pieces of one tile on several CUs meet
+    // only in the global atomics of the flush.
+    const gptr<const int32_t> runs = (gptr<const int32_t>)(I.runs + pbeg);
+    auto run_span = [&](int r, int &rs, int &rl) {
+        const int e = runs[r];
+        rs = min(max(e >> 2, pbeg), pend - 1);
+        rl = min((e & 3) + 1, pend - rs);
+    };
+    if constexpr (KIND == PL_TRACER) {
+        // passive tracers deposit nothing: thread k advances the particles of
+        // runs r_lo + k, + blockDim, ... on their own
+        for (int r = r_lo + (int)threadIdx.x; r < r_hi; r += (int)blockDim.x) {
+            int rs = 0, rl = 0;
+            run_span(r, rs, rl);
+            for (int q = 0; q < rl; ++q) tracer_particle<PREC, SHAPE, DIM>(U, G, S.lds_f, rs + q, err);
+        }
+    } else {
         const int seg = 4 * (int)blockDim.x;
         for (int s0 = r_lo; s0 < r_hi; s0 += seg) {
             const int s1 = min(r_hi, s0 + seg);
@@ -966,13 +1002,112 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
             }
         }
     }
+}
 
+// Claim of the run kernels' next work unit into ctl[0] (or the one claimed
+// before the last flush, pre): false when the launch's units are exhausted;
+// otherwise the unit's item, tile and piece, with t = -1 for an empty or
+// skipped slot.  Item k of the launch owns units [unit_begin + k * kRunsSplit,
+// + nunits + kRunsSplit); the sort lists an item's units largest first as
+// (tile, piece | npieces << 16).
+__device__ __forceinline__ bool runs_claim(const ItemDesc *__restrict__ items, int nitems, int total_units,
+                                           unsigned *counter, int *errflags, int *ctl, bool &pre, int &iti, int &t,
+                                           int &piece, int &npieces)
+{
+    __syncthreads();
+    if (!pre && threadIdx.x == 0) ctl[0] = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    pre = false;
+    t = -1;
+    const int g = __builtin_amdgcn_readfirstlane(ctl[0]);
+    if ((unsigned)g >= (unsigned)total_units) return false;
+    iti = 0;
+    while (iti + 1 < nitems && items[iti + 1].unit_begin + (iti + 1) * kRunsSplit <= g) ++iti;
+    const ItemDesc &I = items[iti];
+    const int ubeg = I.unit_begin + iti * kRunsSplit;
+    const int ucap = I.nunits + kRunsSplit;
+    const int local = g - ubeg;
+    const int nu = min(max(I.runs[runs_count_at(I.np, I.ntiles)], 0), I.nunits > 0 ? ucap : 0);
+    // the sort's tables must cover the item's particles: tile offsets from
+    // 0 to np and at least one unit when np > 0; otherwise the item was
+    // never sorted (or its count changed since): latch it, leave it alone
+    const bool stale = I.tile_start[0] != 0 || I.tile_start[I.ntiles] != I.np || (I.np > 0 && nu == 0);
+    if (stale || local >= nu) {
+        // the rest of this item's units are empty: move the counter past them
+        if (threadIdx.x == 0) {
+            atomicMax(counter, (unsigned)(ubeg + ucap));
+            if (stale) atomicOr(errflags, (int)ERR_UNSORTED);
+        }
+        return true;                                          // uniform
+    }
+    const int32_t *unit = I.runs + runs_units_at(I.np, I.ntiles) + 2 * local;
+    const int tt = unit[0];
+    piece = unit[1] & 0xffff;
+    npieces = unit[1] >> 16;
+    if ((unsigned)tt >= (unsigned)I.ntiles || npieces < 1 || piece >= npieces) return true;      // uniform
+    t = tt;
+    return true;
+}
+
+__device__ __forceinline__ void runs_latch(int err, int *errflags)
+{
     unsigned long long any = __ballot(err != 0);
     if (any) {
         int e = err;
         for (int off = 32; off > 0; off >>= 1) e |= __shfl_xor(e, off, 64);
         if ((threadIdx.x & 63) == 0) atomicOr(errflags, e);
     }
+}
+
+// HF: field halo width (1 or 2) fixed at compile time, or 0 to take it from
+// the launch flags; TS and HF fixed make every LDS stencil offset an
+// immediate.
+template <int PREC, int SHAPE, int DIM, int KIND, int HF, int TS, int CHS>
+__global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_runs(const ItemDesc *__restrict__ items, int nitems, int total_units,
+                                             unsigned *counter, int *errflags, unsigned flags, int lds_bytes)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int *ctl = reinterpret_cast<int *>(smem_raw + lds_bytes - 16);
+    int err = 0;
+    bool pre = false;                      // uniform: ctl[0] already holds the next claim
+    int iti = 0, t = -1, piece = 0, npieces = 1;
+    while (runs_claim(items, nitems, total_units, counter, errflags, ctl, pre, iti, t, piece, npieces)) {
+        if (t < 0) continue;                                  // uniform
+        runs_unit<PREC, SHAPE, DIM, KIND, HF, TS, CHS>(items[iti], t, piece, npieces, flags, lds_bytes, smem_raw,
+                                                      counter, pre, err);
+    }
+    runs_latch(err, errflags);
+    release_counter(counter);
+}
+
+// One persistent launch over the items of every species kind of a call: each
+// claimed unit runs the unit body of its item's kind (uniform per block).
+// CHL and CHD fix the channel sets of the charged (rho J F) and dust (rho F)
+// items, or are 0 to take them at run time.
+template <int PREC, int SHAPE, int DIM, int HF, int TS, int CHL, int CHD>
+__global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_runs_mix(const ItemDesc *__restrict__ items, int nitems, int total_units,
+                                             unsigned *counter, int *errflags, unsigned flags, int lds_bytes)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int *ctl = reinterpret_cast<int *>(smem_raw + lds_bytes - 16);
+    int err = 0;
+    bool pre = false;
+    int iti = 0, t = -1, piece = 0, npieces = 1;
+    while (runs_claim(items, nitems, total_units, counter, errflags, ctl, pre, iti, t, piece, npieces)) {
+        if (t < 0) continue;                                  // uniform
+        const ItemDesc &I = items[iti];
+        const int kind = __builtin_amdgcn_readfirstlane(I.kind);
+        if (kind == PL_LORENTZ)
+            runs_unit<PREC, SHAPE, DIM, PL_LORENTZ, HF, TS, CHL>(I, t, piece, npieces, flags, lds_bytes, smem_raw,
+                                                                 counter, pre, err);
+        else if (kind == PL_DUST)
+            runs_unit<PREC, SHAPE, DIM, PL_DUST, HF, TS, CHD>(I, t, piece, npieces, flags, lds_bytes, smem_raw,
+                                                              counter, pre, err);
+        else
+            runs_unit<PREC, SHAPE, DIM, PL_TRACER, HF, TS, 0>(I, t, piece, npieces, flags, lds_bytes, smem_raw,
+                                                              counter, pre, err);
+    }
+    runs_latch(err, errflags);
     release_counter(counter);
 }
 
@@ -997,67 +1132,100 @@ static StepKernel pick_runs(int shape, int dim, int kind, int hf, int ts, int ch
 }
 
 template <int PREC>
+static StepKernel pick_runs_mix(int shape, int dim, int hf, int ts, int chl, int chd)
+{
+#define PL_M(S, D, HF_, TS_, CL, CD) \
+    if (shape == S && dim == D && hf == HF_ && ts == TS_ && chl == CL && chd == CD) \
+        return k_runs_mix<PREC, S, D, HF_, TS_, CL, CD>;
+    PL_M(PL_TSC, 3, 0, 0, 0, 0) PL_M(PL_TSC, 2, 0, 0, 0, 0) PL_M(PL_CIC, 3, 0, 0, 0, 0) PL_M(PL_CIC, 2, 0, 0, 0, 0)
+    PL_M(PL_TSC, 3, 1, 1, 1, 2) PL_M(PL_TSC, 3, 2, 1, 1, 2) PL_M(PL_TSC, 3, 1, 2, 1, 2) PL_M(PL_TSC, 3, 2, 2, 1, 2)
+#undef PL_M
+    return nullptr;
+}
+
+template <int PREC>
+static size_t runs_item_lds(const Ctx *c, const ItemDesc &it, int hf)
+{
+    const int d3 = c->d.ndim >= 3;
+    const int Lf = (it.tile[0] + 2 * hf) * (it.tile[1] + 2 * hf) * (d3 ? it.tile[2] + 2 * hf : 1);
+    const int Ld = (it.tile[0] + 4) * (it.tile[1] + 4) * (d3 ? it.tile[2] + 4 : 1);
+    size_t offs[6];
+    if (it.kind == PL_LORENTZ) return runs_lds_bytes<PREC, PL_LORENTZ>(Lf, Ld, it.nslot, hf, offs);
+    if (it.kind == PL_DUST) return runs_lds_bytes<PREC, PL_DUST>(Lf, Ld, it.nslot, hf, offs);
+    return runs_lds_bytes<PREC, PL_TRACER>(Lf, Ld, 0, hf, offs);
+}
+
+// Launch configuration of the run kernel for the items of one launch.
+template <int PREC>
+bool runs_plan_impl(const Ctx *c, const ItemDesc *host, int nitems, RunsPlan &pl)
+{
+    pl = RunsPlan{};
+    if (nitems < 1) return false;
+    bool kinds[3] = {false, false, false};
+    for (int i = 0; i < nitems; ++i) kinds[host[i].kind] = true;
+    pl.mixed = kinds[PL_TRACER] || (kinds[PL_LORENTZ] && kinds[PL_DUST]);
+    // compile-time tile shape (8^3 or 8x8x4) and channel sets when every item
+    // allows them: charged rho J F, dust rho F
+    if (c->d.shape == PL_TSC && c->d.ndim == 3) {
+        bool chall = true;
+        for (int i = 0; i < nitems && chall; ++i) {
+            const int want = host[i].kind == PL_LORENTZ ? 1 : (host[i].kind == PL_DUST ? 2 : 0);
+            for (int ch = 0; ch < kMaxCh && want; ++ch) chall = chall && host[i].slot[ch] == chs_slot(want, ch);
+        }
+        for (int cand = 1; cand <= 2 && pl.ts == 0 && chall; ++cand) {
+            bool all = true;
+            for (int i = 0; i < nitems; ++i)
+                for (int a = 0; a < 3; ++a) all = all && host[i].tile[a] == ts_dim(cand, a);
+            if (all) pl.ts = cand;
+        }
+    }
+    if (pl.ts) {
+        pl.chl = 1;
+        pl.chd = 2;
+    }
+    // LDS of the launch: a two-cell field halo when it fits, else one cell
+    for (int hf = 2; hf >= 1; --hf) {
+        size_t lds = 0;
+        for (int i = 0; i < nitems; ++i) lds = std::max(lds, runs_item_lds<PREC>(c, host[i], hf));
+        if (lds <= (size_t)c->lds_max) {
+            pl.hf = hf;
+            pl.lds = lds;
+            return true;
+        }
+    }
+    return false;
+}
+
+template <int PREC>
 hipError_t launch_runs_impl(Ctx *c, const ItemDesc *table, const ItemDesc *host, int nitems, int total_units,
                             unsigned sf, unsigned *counter)
 {
     if (total_units <= 0) return hipSuccess;
-    const int kind = host[0].kind;
-    if (kind == PL_TRACER) return hipErrorInvalidConfiguration;
-    // compile-time tile shape (8^3 or 8x8x4) and channel set when every item
-    // of the group allows them; the generic kernel otherwise
-    int ts = 0, chs = 0;
-    if (c->d.shape == PL_TSC && c->d.ndim == 3) {
-        int want = kind == PL_LORENTZ ? 1 : 2;
-        bool chall = true;
-        for (int i = 0; i < nitems && chall; ++i)
-            for (int ch = 0; ch < kMaxCh; ++ch) chall = chall && host[i].slot[ch] == chs_slot(want, ch);
-        for (int cand = 1; cand <= 2 && ts == 0 && chall; ++cand) {
-            bool all = true;
-            for (int i = 0; i < nitems; ++i)
-                for (int a = 0; a < 3; ++a) all = all && host[i].tile[a] == ts_dim(cand, a);
-            if (all) {
-                ts = cand;
-                chs = want;
-            }
-        }
-    }
-    const int rb = kRunsThreads;
-    // LDS of the group: a two-cell field halo when it fits, else one cell
-    auto group_lds = [&](int hf) {
-        size_t lds = 0;
-        for (int i = 0; i < nitems; ++i) {
-            const ItemDesc &it = host[i];
-            const int d3 = c->d.ndim >= 3;
-            int Lf = (it.tile[0] + 2 * hf) * (it.tile[1] + 2 * hf) * (d3 ? it.tile[2] + 2 * hf : 1);
-            int Ld = (it.tile[0] + 4) * (it.tile[1] + 4) * (d3 ? it.tile[2] + 4 : 1);
-            size_t offs[6];
-            size_t b = kind == PL_LORENTZ ? runs_lds_bytes<PREC, PL_LORENTZ>(Lf, Ld, it.nslot, hf, offs)
-                                          : runs_lds_bytes<PREC, PL_DUST>(Lf, Ld, it.nslot, hf, offs);
-            lds = std::max(lds, b);
-        }
-        return lds;
-    };
-    size_t lds = group_lds(2);
-    int hf = 2;
-    if (lds <= (size_t)c->lds_max) {
-        sf |= SF_FHALO2;
+    RunsPlan pl;
+    if (!runs_plan_impl<PREC>(c, host, nitems, pl)) return hipErrorInvalidConfiguration;
+    if (pl.hf == 2) sf |= SF_FHALO2;
+    StepKernel k;
+    int chs = 0;
+    if (pl.mixed) {
+        // compile-time halo in the fixed-shape kernels, from the flags otherwise
+        k = pick_runs_mix<PREC>(c->d.shape, c->d.ndim, pl.ts ? pl.hf : 0, pl.ts, pl.chl, pl.chd);
+        chs = pl.chl;
     } else {
-        lds = group_lds(1);
-        hf = 1;
-        if (lds > (size_t)c->lds_max) return hipErrorInvalidConfiguration;
+        const int kind = host[0].kind;
+        chs = pl.ts ? (kind == PL_LORENTZ ? pl.chl : pl.chd) : 0;
+        k = pick_runs<PREC>(c->d.shape, c->d.ndim, kind, pl.ts ? pl.hf : 0, pl.ts, chs);
     }
-    // compile-time halo in the fixed-shape kernels, from the flags otherwise
-    StepKernel k = pick_runs<PREC>(c->d.shape, c->d.ndim, kind, ts ? hf : 0, ts, chs);
     if (!k) return hipErrorInvalidConfiguration;
+    const int rb = kRunsThreads;
     // every item has kRunsSplit units beyond its tiles for the pieces of crowded tiles
     const int units = total_units + nitems * kRunsSplit;
-    int grid = std::min(units, resident_blocks(c, k, rb, lds));
-    hipLaunchKernelGGL(k, dim3(grid), dim3(rb), lds, c->stream, table, nitems, units, counter, c->errflags, sf,
-                       (int)lds);
+    int grid = std::min(units, resident_blocks(c, k, rb, pl.lds));
+    hipLaunchKernelGGL(k, dim3(grid), dim3(rb), pl.lds, c->stream, table, nitems, units, counter, c->errflags, sf,
+                       (int)pl.lds);
     c->stats[0]++;
     c->stats[4]++;
-    if (ts) c->stats[6]++;
-    c->stats[7] = ts | chs << 4 | hf << 8;
+    if (pl.ts) c->stats[6]++;
+    c->stats[7] = pl.ts | chs << 4 | pl.hf << 8 | (pl.mixed ? 1 << 12 : 0);
     return hipGetLastError();
 }
 

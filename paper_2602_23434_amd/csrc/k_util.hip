@@ -18,14 +18,24 @@ hipError_t launch_runs_f32(Ctx *c, const ItemDesc *table, const ItemDesc *host, 
 hipError_t launch_runs_f64(Ctx *c, const ItemDesc *table, const ItemDesc *host, int nitems, int total_units,
                            unsigned sf, unsigned *counter);
 
-// The host table is ordered by species kind, then by particle count; every
-// run of one kind is one launch with its own work counter.
+// The host table is ordered by species kind, then by particle count.  A fused
+// run-based step is one launch over every item; otherwise every run of one
+// kind is one launch with its own work counter.
 hipError_t launch_step(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc> &host, int nitems,
                        int total_units, unsigned flags, bool deposit, bool push)
 {
     (void)total_units;
     unsigned sf = (push ? SF_PUSH : 0u) | (deposit ? SF_DEPOSIT : 0u) | ((flags & PL_SUMS) ? SF_SUMS : 0u) |
                   (c->runs ? SF_RUNS : 0u);
+    // a fused run-based step with every kind in one launch (the item table
+    // numbers units across all items then: see build_table)
+    RunsPlan pl;
+    if (c->d.algo == PL_ALGO_RUNS && push && deposit && runs_plan(c, host.data(), nitems, pl)) {
+        int units = 0;
+        for (int i = 0; i < nitems; ++i) units += host[i].nunits;
+        return c->d.prec == PL_F64 ? launch_runs_f64(c, table, host.data(), nitems, units, sf, c->counters)
+                                   : launch_runs_f32(c, table, host.data(), nitems, units, sf, c->counters);
+    }
     int i0 = 0, group = 0;
     while (i0 < nitems) {
         int i1 = i0;

@@ -283,10 +283,19 @@ pl_status build_table(Ctx *c, const pl_item *items, int nitems, double dt, Mode 
     total_units = 0;
     const bool tiled = c->d.algo != PL_ALGO_PLAIN;
     const int chunk = c->block * 4;
+    // a fused run-based step whose LDS fits takes every kind in one launch
+    // (units numbered across all items); otherwise one launch per kind
+    bool one_launch = false;
+    if (c->d.algo == PL_ALGO_RUNS && mode == MODE_STEP && deposit) {
+        std::vector<ItemDesc> all(nitems);
+        for (int k = 0; k < nitems; ++k) all[k] = descs[order[k]];
+        RunsPlan pl;
+        one_launch = runs_plan(c, all.data(), nitems, pl);
+    }
     int group_units = 0;
     for (int k = 0; k < nitems; ++k) {
         ItemDesc D = descs[order[k]];
-        if (k > 0 && D.kind != host.back().kind) group_units = 0;
+        if (k > 0 && D.kind != host.back().kind && !one_launch) group_units = 0;
         D.unit_begin = group_units;
         D.chunk = chunk;
         D.nunits = tiled ? D.ntiles : (D.np + chunk - 1) / chunk;

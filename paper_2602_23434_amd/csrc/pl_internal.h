@@ -147,6 +147,17 @@ struct Ctx {
     std::vector<const void *> fp_stale;
 };
 
+// Launch configuration of the run kernel for one launch's items: field halo,
+// compile-time tile shape (0 generic, 1 8^3, 2 8x8x4), channel sets of the
+// charged (1: rho J F) and dust (2: rho F) items, LDS bytes, and whether the
+// items mix species kinds (one launch dispatching per unit).
+struct RunsPlan {
+    int hf = 0, ts = 0, chl = 0, chd = 0;
+    size_t lds = 0;
+    bool mixed = false;
+};
+bool runs_plan(const Ctx *c, const ItemDesc *host, int nitems, RunsPlan &pl);
+
 // Kernel launchers (k_step.hip)
 hipError_t launch_step(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc> &host, int nitems,
                        int total_units, unsigned flags, bool deposit, bool push);

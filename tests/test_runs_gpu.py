@@ -372,14 +372,19 @@ def test_runs_cic_fp64(mods):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_runs_batched_species(mods, prec):
+    """Charged, dust and tracer items plus small boxes: every step is one
+    launch of the run kernel that takes each unit with its item's kind
+    (pl_part_stats: one run-kernel launch per step, the mixed variant)."""
     oracle, driver, inputs, B = mods
-    say(f"[runs] batched species {prec} (tracers take the tiled kernel)")
+    say(f"[runs] batched species {prec}, one launch per step for every kind")
     wl = _small_batch(inputs)
     ores = oracle.run_workload(wl)
     p = B.PL_F64 if prec == "f64" else B.PL_F32_OFFSET
     run, st = _run_gpu(driver, wl, wl.steps, True, prec=p, algo=B.PL_ALGO_RUNS)
     assert st == B.PL_OK
     _assert_runs_kernel(run, B)
+    stats = B.pl_part_stats(run.ctx)
+    assert stats[4] == wl.steps and stats[7] >> 12 == 1, stats
     f64 = p == B.PL_F64
     for i in range(len(wl.items)):
         _check_item(run, i, ores[i], wl, X_TOL if f64 else 1e-5, U_TOL if f64 else 2e-5,
@@ -464,3 +469,43 @@ def test_sort_first_graph_matches_eager(mods, prec):
     assert st[2] == 4 and st[1] == 12 and st[3] == 4 * len(wl.items), st
     eager.close()
     graph.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("rk", [2, 3])
+def test_runs_tracers_match_tiled(mods, prec, rk):
+    """Tracers in the run kernel (gathers from its LDS field records, the
+    grid for stages whose stencil leaves the field tile): per-id states
+    bit-identical to the tiled kernel's for both Runge-Kutta options, fast
+    enough that stages leave their cell and tile (10 steps, one sort)."""
+    oracle, driver, inputs, B = mods
+    say(f"[runs] tracers {prec} rk{rk}: run kernel vs tiled kernel")
+    n = 16
+    nn = (n, n, n)
+    flds = inputs.turbulent_fields(nn, 1000 + 9, 2000 + 9, v_rms=3.0)
+    rng = np.random.default_rng(3000 + 9)
+    npart = 8 * n ** 3 - 7
+    x = rng.random((3, npart)) * n
+    wl = inputs.Workload(name="tracers", boxes=[inputs.Box(3, nn, {"vg": flds["vg"]})],
+                         species=[inputs.Species("tracer", rk_stages=rk)],
+                         items=[inputs.Item(0, 0, inputs.make_particles(x, np.zeros((3, npart))))], dt=0.1,
+                         steps=10)
+    p = B.PL_F64 if prec == "f64" else B.PL_F32_OFFSET
+    res = {}
+    for algo in (B.PL_ALGO_TILED, B.PL_ALGO_RUNS):
+        kmode = B.PL_KEY_TILE_CELL if algo == B.PL_ALGO_TILED else B.PL_KEY_TILE_RUN
+        run, st = _run_gpu(driver, wl, wl.steps, True, prec=p, algo=algo, tile=(4, 4, 4), key_mode=kmode)
+        assert st in (B.PL_OK, B.PL_ECFL)
+        if algo == B.PL_ALGO_RUNS:
+            stats = B.pl_part_stats(run.ctx)
+            assert stats[4] == wl.steps and stats[5] == 0, stats
+        raw = run.raw(0)
+        ids = raw["id"].astype(np.int64)
+        res[algo] = {k: _cmp.by_id(np.stack(v) if isinstance(v, list) else v, ids) for k, v in raw.items()
+                     if k in ("x", "u", "cell")}
+        run.close()
+    a, b = res[B.PL_ALGO_TILED], res[B.PL_ALGO_RUNS]
+    moved = np.abs(a["u"]).max()
+    say(f"  largest tracer speed {moved:.2f} cells per unit time")
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
