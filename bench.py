@@ -184,12 +184,16 @@ def time_workload(wl, cfg, steps, every, torch, B, driver):
         timed_loop(run, 2, every, True, torch, B)
         ms, kern, sorts = timed_loop(run, steps, every, True, torch, B)
         stats = B.pl_part_stats(run.ctx)
-        # the charged items alone, one call per step (their own launch)
+        # the charged items alone, one call per step (their own launch), at the
+        # same sort cadence; the steps without a sort are timed
         ci = [i for i, it in enumerate(wl.items) if wl.species[it.species].kind == "lorentz"]
         sub = (B.pl_item * len(ci))(*[run.items[i] for i in ci])
         ev = lambda: torch.cuda.Event(enable_timing=True)
         pairs = []
-        for _ in range(steps):
+        for s in range(steps):
+            if s % every == 0:
+                run.step(flags=B.PL_FUSE_DEPOSIT | B.PL_ZERO_FIRST | B.PL_GRAPH | B.PL_SORT_FIRST, items=sub)
+                continue
             run.zero_moments()
             a, b = ev(), ev()
             a.record(run.stream)
@@ -213,9 +217,11 @@ def extra_workloads(head_cfg, torch, B, driver, inputs):
     """The clumped 256^3 box (2^26 particles, half in 32 Gaussian clumps, sort
     every 4 steps) and the batched workload (192^3 box with charged, dust and
     tracer species plus 16 independent 64^3 boxes), both in the float32 form
-    with the headline's kernel configuration, 20 steps each, each with its
-    roofline: algorithmic bytes of the charged run kernel's launch over its
-    time, and of the whole step (sort amortised) over the step time."""
+    (the clumped box in the headline's configuration, the batched workload in
+    its own tuned one), timed over a whole number of sort periods of at least
+    20 steps, each with its roofline: algorithmic bytes of the charged run
+    kernel's launch over its time, and of the whole step (sort amortised) over
+    the step time."""
     from paper_2602_23434_amd import benchcfg as BC
     out = {}
     bcfg = BC.batched_cfg()
@@ -233,7 +239,9 @@ def extra_workloads(head_cfg, torch, B, driver, inputs):
             per_box[bidx] = touched_cells(np.concatenate(xs, axis=1), wl.boxes[bidx].n) if len(xs) > 1 \
                 else per_box[bidx]
         log(f"[bench] {name}: inputs in {time.perf_counter() - t0:.1f} s")
-        r = time_workload(wl, wcfg, 20, every, torch, B, driver)
+        # a whole number of sort periods, at least 20 steps
+        nsteps = every * max(2, -(-20 // every))
+        r = time_workload(wl, wcfg, nsteps, every, torch, B, driver)
         r["config"] = {"tile": list(wcfg["tile"]), "sort_key": wcfg["key_mode"]}
         step_bytes, charged_bytes = workload_bytes(wl, per_box)
         npart = sum(it.particles.n for it in wl.items)

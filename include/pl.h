@@ -165,7 +165,9 @@ typedef struct {
                                         with PL_ALGO_RUNS: 512, the run-based kernel's block);
                                         0 = default */
     void *stream;                    /* hipStream_t for all work; NULL = the null stream */
-    const char *tune_cache;          /* nullable: file written by the autotuner (block, tile) */
+    const char *tune_cache;          /* nullable: file written by the autotuner ("key value" lines: block,
+                                        runs_block, tile, and one_launch 0 to give each species kind its
+                                        own launch in fused run-based steps) */
 } pl_init_desc;
 
 /*
@@ -252,7 +254,8 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d);
  * this call.  With PL_ALGO_RUNS and PL_FUSE_DEPOSIT every item of the call,
  * of every species kind, goes to one persistent launch whose blocks claim
  * (item, tile piece) work units from one counter and run each with its
- * item's kind; otherwise the items of each kind share one launch.
+ * item's kind (unless the tune cache says one_launch 0); otherwise the items
+ * of each kind share one launch.
  *   PL_FUSE_DEPOSIT  deposit the items' non-NULL moment channels at x^{n+1}
  *                    in the same pass (added to the grids' contents);
  *   PL_ZERO_FIRST    zero those channels first;

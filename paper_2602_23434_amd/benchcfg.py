@@ -57,11 +57,12 @@ def batched_cfg():
     import os
 
     from . import tune
-    if os.path.exists(tune.tune_file(B.PL_F32_OFFSET, batched=True)):
-        cfg = _tuned(F32_RUNS, B.PL_F32_OFFSET, batched=True)
+    path = tune.tune_file(B.PL_F32_OFFSET, batched=True)
+    if os.path.exists(path):
+        cfg = dict(_tuned(F32_RUNS, B.PL_F32_OFFSET, batched=True))
+        cfg["tune_cache"] = path            # the library reads its launch choice there
     else:
-        cfg = headline()
-    cfg = dict(cfg)
+        cfg = dict(headline())
     cfg["channels"] = None
     return cfg
 

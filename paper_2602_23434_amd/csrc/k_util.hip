@@ -30,7 +30,7 @@ hipError_t launch_step(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc
     // a fused run-based step with every kind in one launch (the item table
     // numbers units across all items then: see build_table)
     RunsPlan pl;
-    if (c->d.algo == PL_ALGO_RUNS && push && deposit && runs_plan(c, host.data(), nitems, pl)) {
+    if (c->one_launch && c->d.algo == PL_ALGO_RUNS && push && deposit && runs_plan(c, host.data(), nitems, pl)) {
         int units = 0;
         for (int i = 0; i < nitems; ++i) units += host[i].nunits;
         return c->d.prec == PL_F64 ? launch_runs_f64(c, table, host.data(), nitems, units, sf, c->counters)

@@ -78,7 +78,7 @@ int divisor_at_most(int n, int want)
     return 1;
 }
 
-void read_tune_cache(const char *path, int &block, int tile[3], int &runs, int &runs_block)
+void read_tune_cache(const char *path, int &block, int tile[3], int &runs, int &runs_block, int &one_launch)
 {
     if (!path) return;
     FILE *f = fopen(path, "r");
@@ -91,6 +91,9 @@ void read_tune_cache(const char *path, int &block, int tile[3], int &runs, int &
         } else if (!strcmp(key, "runs")) {
             int v;
             if (fscanf(f, "%d", &v) == 1) runs = v != 0;
+        } else if (!strcmp(key, "one_launch")) {
+            int v;
+            if (fscanf(f, "%d", &v) == 1) one_launch = v != 0;
         } else if (!strcmp(key, "runs_block")) {
             int v;
             if (fscanf(f, "%d", &v) == 1 && v == 512) runs_block = v;
@@ -286,7 +289,7 @@ pl_status build_table(Ctx *c, const pl_item *items, int nitems, double dt, Mode 
     // a fused run-based step whose LDS fits takes every kind in one launch
     // (units numbered across all items); otherwise one launch per kind
     bool one_launch = false;
-    if (c->d.algo == PL_ALGO_RUNS && mode == MODE_STEP && deposit) {
+    if (c->one_launch && c->d.algo == PL_ALGO_RUNS && mode == MODE_STEP && deposit) {
         std::vector<ItemDesc> all(nitems);
         for (int k = 0; k < nitems; ++k) all[k] = descs[order[k]];
         RunsPlan pl;
@@ -477,10 +480,11 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d)
     c->max_np = d->max_np;
     c->fp_stale.reserve(4 * (size_t)d->max_items + 16);
 
-    int tuned_block = 256, tuned_tile[3] = {8, 8, 8}, tuned_runs = 0, tuned_runs_block = 512;
+    int tuned_block = 256, tuned_tile[3] = {8, 8, 8}, tuned_runs = 0, tuned_runs_block = 512, tuned_one = 1;
     if (d->prec == PL_F64 && d->algo == PL_ALGO_TILED) { tuned_tile[1] = 4; tuned_tile[2] = 4; }
     if (d->prec == PL_F64 && d->algo == PL_ALGO_RUNS) tuned_tile[2] = 4;
-    read_tune_cache(d->tune_cache, tuned_block, tuned_tile, tuned_runs, tuned_runs_block);
+    read_tune_cache(d->tune_cache, tuned_block, tuned_tile, tuned_runs, tuned_runs_block, tuned_one);
+    c->one_launch = tuned_one != 0;
     const bool runs_algo = d->algo == PL_ALGO_RUNS;
     c->block = (d->block && !runs_algo) ? d->block : tuned_block;
     c->runs = tuned_runs != 0;

@@ -111,6 +111,8 @@ struct Ctx {
     int lds_max = 65536;
     bool runs = false;               // tiled: contiguous per-thread particle runs (tune cache "runs 1")
     int runs_block = 512;            // block size of the run-based kernels (init block or tune cache "runs_block")
+    bool one_launch = true;          // fused run-based steps over several kinds: one launch (tune cache
+                                     // "one_launch 0": one launch per kind)
 
     // device scratch
     ItemDesc *table = nullptr;       // max_items descriptors for non-graph calls

@@ -509,3 +509,36 @@ def test_runs_tracers_match_tiled(mods, prec, rk):
     say(f"  largest tracer speed {moved:.2f} cells per unit time")
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_one_launch_matches_per_kind(mods, tmp_path):
+    """The batched species workload with every kind in one launch and, from a
+    tune cache with one_launch 0, with one launch per kind: per-id particle
+    states bit-identical, deposits equal to round-off."""
+    oracle, driver, inputs, B = mods
+    say("[runs] one launch for every kind vs one launch per kind")
+    wl = _small_batch(inputs)
+    cache = tmp_path / "per_kind.txt"
+    cache.write_text("one_launch 0\n")
+    res = []
+    for tc in (None, str(cache)):
+        run, st = _run_gpu(driver, wl, wl.steps, True, prec=B.PL_F32_OFFSET, algo=B.PL_ALGO_RUNS, tune_cache=tc)
+        assert st == B.PL_OK
+        stats = B.pl_part_stats(run.ctx)
+        # per kind: charged and dust in run kernels, tracers in the tiled kernel
+        assert stats[4] == (wl.steps if tc is None else 2 * wl.steps), stats
+        out = []
+        for i in range(len(wl.items)):
+            raw = run.raw(i)
+            ids = raw["id"].astype(np.int64)
+            out.append(({k: _cmp.by_id(np.stack(v) if isinstance(v, list) else v, ids) for k, v in raw.items()
+                         if k in ("x", "u", "cell")}, run.moments(i)))
+        res.append(out)
+        run.close()
+    for i in range(len(wl.items)):
+        (sa, ma), (sb, mb) = res[0][i], res[1][i]
+        for k in sa:
+            assert np.array_equal(sa[k], sb[k]), (i, k)
+        for k in ma:
+            va, vb = np.asarray(ma[k]), np.asarray(mb[k])
+            assert np.abs(va - vb).max() <= 2e-6 * max(np.abs(va).max(), 1e-300), (i, k)
