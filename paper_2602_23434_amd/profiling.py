@@ -8,9 +8,10 @@ summaries kept beside the sources.
         dispatch carries its own counters.  Run it under
         `rocprofv3 --pmc FETCH_SIZE` and again under `--pmc WRITE_SIZE`.
 
-    python -m paper_2602_23434_amd.profiling trace-md DB TITLE COMMAND
+    python -m paper_2602_23434_amd.profiling trace-md DB TITLE COMMAND [--split K=label:n,...]
         markdown table of the top kernels of a `--kernel-trace --stats`
-        database.
+        database; --split adds the average of one kernel's dispatches per
+        consecutive group (the workloads of the benchmark, in order).
 
     python -m paper_2602_23434_amd.profiling traffic FETCH_CSV WRITE_CSV COMMAND
         HBM bytes per launch of the run kernel as JSON: each counter's mean
@@ -87,6 +88,24 @@ def trace_md(db, title, command):
            "| kernel | calls | average (ms) | total (ms) | share |", "|---|---:|---:|---:|---:|"]
     for name, calls, tot, avg, pct in rows[:20]:
         out.append(f"| `{name.split('(')[0]}` | {calls} | {avg / 1e3:.4f} | {tot / 1e3:.2f} | {pct:.1f}% |")
+    return "\n".join(out) + "\n"
+
+
+def split_md(db, kernel, parts):
+    """Markdown rows for the dispatches of one kernel split into consecutive
+    groups, in dispatch order: parts is a list of (label, count)."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, duration from kernels order by start").fetchall()
+    durs = [d for n, d in rows if n.split("(")[0].replace("void ", "") == kernel]
+    if sum(c for _, c in parts) != len(durs):
+        raise RuntimeError(f"{len(durs)} dispatches of {kernel}, parts {parts}")
+    out = [f"\nDispatches of `{kernel}` by workload, in order:\n", "| workload | calls | average (ms) |",
+           "|---|---:|---:|"]
+    i = 0
+    for label, cnt in parts:
+        seg = durs[i:i + cnt]
+        i += cnt
+        out.append(f"| {label} | {cnt} | {sum(seg) / len(seg) / 1e6:.4f} |")
     return "\n".join(out) + "\n"
 
 
@@ -184,6 +203,8 @@ def main(argv=None):
     t.add_argument("db")
     t.add_argument("title")
     t.add_argument("command")
+    t.add_argument("--split", default=None,
+                   help="KERNEL=label:count,label:count,... per-workload averages of one kernel's dispatches")
     c = sub.add_parser("traffic")
     c.add_argument("fetch_csv")
     c.add_argument("write_csv")
@@ -196,6 +217,10 @@ def main(argv=None):
         workload(a.steps)
     elif a.cmd == "trace-md":
         sys.stdout.write(trace_md(a.db, a.title, a.command))
+        if a.split:
+            kern, spec = a.split.split("=", 1)
+            parts = [(p.rsplit(":", 1)[0], int(p.rsplit(":", 1)[1])) for p in spec.split(",")]
+            sys.stdout.write(split_md(a.db, kern, parts))
     elif a.cmd == "instructions":
         print(json.dumps(instructions(a.sq_csv, a.command), indent=1))
     else:
