@@ -159,9 +159,10 @@ __device__ __forceinline__ void push_particle(const UnitC<PREC> &U, typename Rea
         R u_old2 = fma(u[0], u[0], fma(u[1], u[1], u[2] * u[2]));
         boris<R>(u, F, F + 3, U.h, U.inv_c2, du);
         R u_new2 = fma(u[0], u[0], fma(u[1], u[1], u[2] * u[2]));
-        R gn = sqrt(fma(u_new2, U.inv_c2, R(1)));
+        const R gn2 = fma(u_new2, U.inv_c2, R(1));
+        R gn = sqrt(gn2);
         R go = sqrt(fma(u_old2, U.inv_c2, R(1)));
-        R ig = R(1) / gn;
+        R ig = div_sqrt_ge1(R(1), gn2);
 #pragma unroll
         for (int a = 0; a < 3; ++a) v[a] = u[a] * ig;
         R qw = U.q * w, mw = U.m * w;

@@ -245,9 +245,16 @@ template <int DIM> struct Pos<PL_F32_OFFSET, DIM> {
             float o = (float)(s - sh);
             int shift = (int)sh;
             if (o >= 0.5f) { o = -0.5f; shift += 1; }
-            int nn = it.n[a];
-            int ci = (c[a] + shift) % nn;
+            // periodic wrap: one correction covers every step within the
+            // CFL limit (|shift| <= 2); the remainder only after a violation
+            const int nn = it.n[a];
+            int ci = c[a] + shift;
             if (ci < 0) ci += nn;
+            else if (ci >= nn) ci -= nn;
+            if ((unsigned)ci >= (unsigned)nn) {
+                ci %= nn;
+                if (ci < 0) ci += nn;
+            }
             c[a] = ci;
             d[a] = o;
         }
@@ -259,6 +266,15 @@ template <int DIM> struct Pos<PL_F32_OFFSET, DIM> {
 // without the cancellation of u_new - u_old) and update u in place.
 // ---------------------------------------------------------------------------
 
+// a/sqrt(x) and a/x for x >= 1 (a Lorentz factor squared, 1 + |t|^2).
+// Float32: a times the hardware reciprocal square root or reciprocal (1 ulp
+// each; the correctly rounded forms take about ten instructions each, a
+// tenth of the push).  Float64: the correctly rounded quotient.
+__device__ __forceinline__ float div_sqrt_ge1(float a, float x) { return a * __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double div_sqrt_ge1(double a, double x) { return a / sqrt(x); }
+__device__ __forceinline__ float div_ge1(float a, float x) { return a * __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double div_ge1(double a, double x) { return a / x; }
+
 // Relativistic Boris push (Boris 1970) for du/dt = (q/m)(E + u/gamma x B):
 // half electric kick, rotation about B by 2 atan(|t|), half electric kick.
 // The change is du = 2 h E + (u' x s), with u' = u- + u- x t.
@@ -267,10 +283,10 @@ __device__ __forceinline__ void boris(R u[3], const R E[3], const R B[3], R h, R
 {
     R hE[3] = {h * E[0], h * E[1], h * E[2]};
     R um[3] = {u[0] + hE[0], u[1] + hE[1], u[2] + hE[2]};
-    R g = sqrt(fma(fma(um[0], um[0], fma(um[1], um[1], um[2] * um[2])), inv_c2, R(1)));
-    R hg = h / g;
+    const R g2 = fma(fma(um[0], um[0], fma(um[1], um[1], um[2] * um[2])), inv_c2, R(1));
+    const R hg = div_sqrt_ge1(h, g2);
     R t[3] = {hg * B[0], hg * B[1], hg * B[2]};
-    R f = R(2) / (R(1) + fma(t[0], t[0], fma(t[1], t[1], t[2] * t[2])));
+    const R f = div_ge1(R(2), R(1) + fma(t[0], t[0], fma(t[1], t[1], t[2] * t[2])));
     R s[3] = {f * t[0], f * t[1], f * t[2]};
     R uc[3] = {um[0] + fma(um[1], t[2], -(um[2] * t[1])),
                um[1] + fma(um[2], t[0], -(um[0] * t[2])),
