@@ -327,15 +327,22 @@ __global__ void k_rank_keys(uint32_t *keys, int np, const int32_t *cs, int cell_
 // (first position << 2) | (length - 1), stored from runs[tile_start[t]];
 // the tile's run count goes to runs[np + t].  With perm_out (run order) the
 // runs are laid out one after another in table order from tile_start[t]: the
-// entries hold those positions, and perm_out[new position] = perm_in[sorted
-// position] composes the move with the sort's permutation.
+// entries hold those positions, and perm_out[new position] = sorted position
+// (k_compose_perm then composes it with the sort's permutation).  The first
+// kRunsDense rounds (run index inside the cell) take one block scan each; the
+// cells with more runs (crowded cells of clumped particles, up to hundreds of
+// rounds) are then listed in cell order and one wave takes the remaining
+// rounds, dropping every cell from the list after its last run.
 constexpr int kRunsBuildThreads = 256;
+constexpr int kRunsDense = 8;
+static_assert(kRunLen == 4, "the crowded rounds' ballot prefix sums take run shortfalls of two bits");
 __global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t *keys, int np, int per_tile,
                                                                   int ntiles, const int32_t *ts, int32_t *runs,
-                                                                  const uint32_t *perm_in, uint32_t *perm_out)
+                                                                  uint32_t *perm_out)
 {
     __shared__ int cnt[kRunsMaxTileCells];
     __shared__ int first[kRunsMaxTileCells];
+    __shared__ int4 crowd[kRunsMaxTileCells];
     __shared__ uint32_t sh[kRunsBuildThreads / 64 + 1];
     __shared__ int s_max;
     const int cpt = (per_tile + kRunsBuildThreads - 1) / kRunsBuildThreads;   // cells per thread
@@ -345,30 +352,46 @@ __global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t
         for (int c = threadIdx.x; c < per_tile; c += blockDim.x) cnt[c] = 0;
         if (threadIdx.x == 0) s_max = 0;
         __syncthreads();
+        // first sorted position and end of every cell from the key boundaries
+        // (the keys are sorted): each thread scans a contiguous stretch, so a
+        // crowded tile's particles are read with many loads in flight and
+        // without atomics
         const uint32_t kb = (uint32_t)t * (uint32_t)per_tile;
-        for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
-            uint32_t loc = keys[p] - kb;
-            if (loc < (uint32_t)per_tile) atomicAdd(&cnt[loc], 1);
+        {
+            const int n = end - beg;
+            const int per = (n + (int)blockDim.x - 1) / (int)blockDim.x;
+            const int q0 = beg + min(n, (int)threadIdx.x * per);
+            const int q1 = beg + min(n, ((int)threadIdx.x + 1) * per);
+            if (q0 < q1) {
+                uint32_t prev = q0 > beg ? keys[q0 - 1] : ~0u;
+                bool open = q0 > beg;                // prev's cell continues into this stretch
+#pragma unroll 8
+                for (int p = q0; p < q1; ++p) {
+                    const uint32_t k = keys[p];
+                    if (k != prev) {
+                        if (open && prev - kb < (uint32_t)per_tile) cnt[prev - kb] = p;   // one past its last
+                        if (k - kb < (uint32_t)per_tile) first[k - kb] = p;
+                        open = true;
+                    }
+                    prev = k;
+                }
+                if ((q1 == end || keys[q1] != prev) && prev - kb < (uint32_t)per_tile) cnt[prev - kb] = q1;
+            }
         }
         __syncthreads();
-        // first sorted position of every cell, and the largest run count
-        uint32_t mine = 0;
+        // counts, and the largest run count
         int mx = 0;
         for (int c = c0; c < c1; ++c) {
-            mine += (uint32_t)cnt[c];
+            if (cnt[c] > 0) cnt[c] -= first[c];
             mx = max(mx, (cnt[c] + kRunLen - 1) / kRunLen);
         }
         uint32_t total;
-        uint32_t run = block_exclusive_scan(mine, sh, total);
-        for (int c = c0; c < c1; ++c) {
-            first[c] = beg + (int)run;
-            run += (uint32_t)cnt[c];
-        }
         atomicMax(&s_max, mx);
         __syncthreads();
         const int nb = s_max;
+        const int nb0 = min(nb, kRunsDense);
         int base = 0, lbase = 0;
-        for (int b = 0; b < nb; ++b) {
+        for (int b = 0; b < nb0; ++b) {
             // runs (high half) and particles (low half) of this round before my
             // cells: at most 1024 runs and 4096 particles, so the halves never carry
             uint32_t here = 0;
@@ -386,7 +409,7 @@ __global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t
                     const int dst = perm_out ? beg + lbase + lpos : src;
                     runs[beg + base + pos] = (dst << 2) | (len - 1);
                     if (perm_out)
-                        for (int i = 0; i < len; ++i) perm_out[dst + i] = perm_in[src + i];
+                        for (int i = 0; i < len; ++i) perm_out[dst + i] = (uint32_t)(src + i);
                     ++pos;
                     lpos += len;
                 }
@@ -394,9 +417,70 @@ __global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t
             base += (int)(total >> 16);
             lbase += (int)(total & 0xffffu);
         }
+        if (nb > nb0) {
+            // cells with more than nb0 runs, in cell order: (cell, first
+            // sorted position, particle count)
+            uint32_t mine_c = 0;
+            for (int c = c0; c < c1; ++c) mine_c += cnt[c] > nb0 * kRunLen ? 1u : 0u;
+            uint32_t k = block_exclusive_scan(mine_c, sh, total);
+            for (int c = c0; c < c1; ++c)
+                if (cnt[c] > nb0 * kRunLen) crowd[k++] = make_int4(c, first[c], cnt[c], 0);
+            __syncthreads();
+            if (threadIdx.x < 64) {
+                // one wave, round by round: every listed cell has a run in
+                // this round; lanes take the list 64 cells at a time, and the
+                // cells that still have runs are compacted to the front
+                const int lane = threadIdx.x;
+                const uint64_t lt = (1ull << lane) - 1ull;
+                int K = (int)total;
+                for (int b = nb0; b < nb && K > 0; ++b) {
+                    int kept = 0, rpos = 0, ppos = 0;
+                    for (int j0 = 0; j0 < K; j0 += 64) {
+                        const int j = j0 + lane;
+                        const bool in = j < K;
+                        const int4 e = in ? crowd[j] : make_int4(0, 0, 0, 0);
+                        const int left = e.z - b * kRunLen;
+                        const int len = in ? min(kRunLen, left) : 0;
+                        // prefix sums of the run lengths from ballots: kRunLen
+                        // per active lane minus the shortfall d = kRunLen - len
+                        // (0..3) of the cells' last runs
+                        const int d = in ? kRunLen - len : 0;
+                        const uint64_t am = __ballot(in);
+                        const uint64_t d0 = __ballot(d & 1), d1 = __ballot(d & 2);
+                        const int lpre = kRunLen * __popcll(am & lt) - __popcll(d0 & lt) - 2 * __popcll(d1 & lt);
+                        const int lsum = kRunLen * __popcll(am) - __popcll(d0) - 2 * __popcll(d1);
+                        if (in) {
+                            const int pos = rpos + __popcll(am & lt);
+                            const int src = e.y + b * kRunLen;
+                            const int dst = perm_out ? beg + lbase + ppos + lpre : src;
+                            runs[beg + base + pos] = (dst << 2) | (len - 1);
+                            if (perm_out)
+                                for (int i = 0; i < len; ++i) perm_out[dst + i] = (uint32_t)(src + i);
+                        }
+                        rpos += __popcll(am);
+                        ppos += lsum;
+                        // the list is read ahead of every write (kept <= j0)
+                        const bool keep = in && left > kRunLen;
+                        const uint64_t km = __ballot(keep);
+                        if (keep) crowd[kept + __popcll(km & lt)] = e;
+                        kept += __popcll(km);
+                    }
+                    base += rpos;
+                    lbase += ppos;
+                    K = kept;
+                }
+            }
+        }
         if (threadIdx.x == 0) runs[np + t] = base;
         __syncthreads();
     }
+}
+
+// perm[q] = perm_in[perm[q]]: new position -> sorted position -> source
+// index.
+__global__ void k_compose_perm(uint32_t *perm, const uint32_t *perm_in, int np)
+{
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < np; q += gridDim.x * blockDim.x) perm[q] = perm_in[perm[q]];
 }
 
 // Work units of the run-based kernel (one block).  With P = max(ceil(total
@@ -579,12 +663,14 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
         if (!a.runs) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_tile_start, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, 0, div, a.ntiles,
                            a.tile_start);
-        hipLaunchKernelGGL(k_runs_build, dim3(std::min(a.ntiles, 8 * c->num_cu)), dim3(kRunsBuildThreads), 0, s,
-                           c->keys[src], a.np, per_tile_cells, a.ntiles, a.tile_start, a.runs,
-                           (const uint32_t *)c->idx[src], c->idx[1 - src]);
+        // one block per tile: a crowded tile's rounds do not hold up others
+        hipLaunchKernelGGL(k_runs_build, dim3(std::max(a.ntiles, 1)), dim3(kRunsBuildThreads), 0, s,
+                           c->keys[src], a.np, per_tile_cells, a.ntiles, a.tile_start, a.runs, c->idx[1 - src]);
+        hipLaunchKernelGGL(k_compose_perm, dim3(grid_e), dim3(256), 0, s, c->idx[1 - src],
+                           (const uint32_t *)c->idx[src], a.np);
         permute_arrays(c, a, c->idx[1 - src], grid_e);
         hipLaunchKernelGGL(k_unit_list, dim3(1), dim3(kOrderThreads), 0, s, a.runs, a.np, a.ntiles);
-        c->stats[0] += 3;
+        c->stats[0] += 4;
         return hipGetLastError();
     }
     permute_arrays(c, a, c->idx[src], grid_e);
@@ -593,8 +679,8 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
     c->stats[0]++;
     if (a.runs) {
         // keys are tile * cells_per_tile + cell in tile (PL_KEY_TILE_CELL)
-        hipLaunchKernelGGL(k_runs_build, dim3(std::min(a.ntiles, 8 * c->num_cu)), dim3(kRunsBuildThreads), 0, s,
-                           c->keys[src], a.np, per_tile_cells, a.ntiles, a.tile_start, a.runs, nullptr, nullptr);
+        hipLaunchKernelGGL(k_runs_build, dim3(std::max(a.ntiles, 1)), dim3(kRunsBuildThreads), 0, s,
+                           c->keys[src], a.np, per_tile_cells, a.ntiles, a.tile_start, a.runs, nullptr);
         hipLaunchKernelGGL(k_unit_list, dim3(1), dim3(kOrderThreads), 0, s, a.runs, a.np, a.ntiles);
         c->stats[0] += 2;
     }

@@ -146,10 +146,13 @@ def relaid_runs(exp, tstart, npart, ntiles):
 def test_runs_table_exact(mods, prec, key):
     oracle, driver, inputs, B = mods
     kmode = B.PL_KEY_TILE_CELL if key == "cell" else B.PL_KEY_TILE_RUN
+    # 40 per cell: most cells of every 8^3 tile hold more than eight runs (the
+    # run-table build takes the rounds beyond eight with one wave)
     for n, npart, tile in ((32, 8 * 32 ** 3 - 37, (8, 8, 8)), (16, 1, (4, 4, 4)), (16, 3001, (16, 8, 2)),
-                           (16, 20000, (4, 4, 4)), (32, -1, (4, 4, 4)), (32, -2, (4, 4, 4))):
+                           (16, 20000, (4, 4, 4)), (16, 40 * 16 ** 3 + 5, (8, 8, 8)), (32, -1, (4, 4, 4)),
+                           (32, -2, (4, 4, 4)), (32, -2, (8, 8, 8))):
         say(f"[runs] run table {prec} key {key} n={n} np={npart} tile={tile}")
-        split = npart < 0
+        split = npart < 0 and tile == (4, 4, 4)
         if npart < 0:
             # clumped: crowded tiles cut into pieces that go first in the order
             ck = dict(npart=60000, nclumps=3, sigma=1.5) if npart == -1 else dict(npart=200000, nclumps=2, sigma=1.0)
