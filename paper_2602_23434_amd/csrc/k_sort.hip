@@ -343,6 +343,7 @@ __global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t
     __shared__ int cnt[kRunsMaxTileCells];
     __shared__ int first[kRunsMaxTileCells];
     __shared__ int4 crowd[kRunsMaxTileCells];
+    __shared__ int wl[(kRunsBuildThreads / 64) * kRunsMaxTileCells];
     __shared__ uint32_t sh[kRunsBuildThreads / 64 + 1];
     __shared__ int s_max;
     const int cpt = (per_tile + kRunsBuildThreads - 1) / kRunsBuildThreads;   // cells per thread
@@ -353,39 +354,60 @@ __global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t
         if (threadIdx.x == 0) s_max = 0;
         __syncthreads();
         // first sorted position and end of every cell from the key boundaries
-        // (the keys are sorted): each thread scans a contiguous stretch, so a
-        // crowded tile's particles are read with many loads in flight and
-        // without atomics
+        // (the keys are sorted: no atomics, crowded cells included).  Each
+        // thread takes four consecutive keys per 16-byte load and issues the
+        // loads of KB such groups before using any.
         const uint32_t kb = (uint32_t)t * (uint32_t)per_tile;
         {
-            const int n = end - beg;
-            const int per = (n + (int)blockDim.x - 1) / (int)blockDim.x;
-            const int q0 = beg + min(n, (int)threadIdx.x * per);
-            const int q1 = beg + min(n, ((int)threadIdx.x + 1) * per);
-            if (q0 < q1) {
-                uint32_t prev = q0 > beg ? keys[q0 - 1] : ~0u;
-                bool open = q0 > beg;                // prev's cell continues into this stretch
-#pragma unroll 8
-                for (int p = q0; p < q1; ++p) {
-                    const uint32_t k = keys[p];
-                    if (k != prev) {
-                        if (open && prev - kb < (uint32_t)per_tile) cnt[prev - kb] = p;   // one past its last
-                        if (k - kb < (uint32_t)per_tile) first[k - kb] = p;
-                        open = true;
+            typedef uint32_t U4 __attribute__((ext_vector_type(4), aligned(4)));
+            constexpr int KB = 8;
+            const int bd = (int)blockDim.x;
+            for (int p0 = beg + 4 * (int)threadIdx.x; p0 < end; p0 += 4 * KB * bd) {
+                uint32_t kc[KB][4], kp[KB], kn[KB];
+#pragma unroll
+                for (int i = 0; i < KB; ++i) {
+                    const int p = p0 + 4 * i * bd;
+                    if (p + 4 <= end) {
+                        const U4 v = *reinterpret_cast<const U4 *>(keys + p);
+                        kc[i][0] = v[0];
+                        kc[i][1] = v[1];
+                        kc[i][2] = v[2];
+                        kc[i][3] = v[3];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) kc[i][q] = p + q < end ? keys[p + q] : ~0u;
                     }
-                    prev = k;
+                    kp[i] = p < end && p > beg ? keys[p - 1] : ~0u;
+                    kn[i] = p + 4 < end ? keys[p + 4] : ~0u;
                 }
-                if ((q1 == end || keys[q1] != prev) && prev - kb < (uint32_t)per_tile) cnt[prev - kb] = q1;
+#pragma unroll
+                for (int i = 0; i < KB; ++i) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int p = p0 + 4 * i * bd + q;
+                        const uint32_t k = kc[i][q];
+                        const uint32_t before = q == 0 ? kp[i] : kc[i][q - 1];
+                        const uint32_t after = q == 3 ? kn[i] : kc[i][q + 1];
+                        const uint32_t loc = k - kb;
+                        if (p < end && loc < (uint32_t)per_tile) {
+                            if (before != k) first[loc] = p;
+                            if (after != k) cnt[loc] = p + 1;        // one past the cell's last
+                        }
+                    }
+                }
             }
         }
         __syncthreads();
-        // counts, and the largest run count
+        // counts, the largest run count and the tile's run count
         int mx = 0;
+        uint32_t mruns = 0;
         for (int c = c0; c < c1; ++c) {
             if (cnt[c] > 0) cnt[c] -= first[c];
             mx = max(mx, (cnt[c] + kRunLen - 1) / kRunLen);
+            mruns += (uint32_t)((cnt[c] + kRunLen - 1) / kRunLen);
         }
-        uint32_t total;
+        uint32_t total, truns;
+        block_exclusive_scan(mruns, sh, truns);
         atomicMax(&s_max, mx);
         __syncthreads();
         const int nb = s_max;
@@ -426,50 +448,72 @@ __global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t
             for (int c = c0; c < c1; ++c)
                 if (cnt[c] > nb0 * kRunLen) crowd[k++] = make_int4(c, first[c], cnt[c], 0);
             __syncthreads();
-            if (threadIdx.x < 64) {
-                // one wave, round by round: every listed cell has a run in
-                // this round; lanes take the list 64 cells at a time, and the
-                // cells that still have runs are compacted to the front
-                const int lane = threadIdx.x;
-                const uint64_t lt = (1ull << lane) - 1ull;
-                int K = (int)total;
-                for (int b = nb0; b < nb && K > 0; ++b) {
-                    int kept = 0, rpos = 0, ppos = 0;
-                    for (int j0 = 0; j0 < K; j0 += 64) {
-                        const int j = j0 + lane;
-                        const bool in = j < K;
-                        const int4 e = in ? crowd[j] : make_int4(0, 0, 0, 0);
-                        const int left = e.z - b * kRunLen;
-                        const int len = in ? min(kRunLen, left) : 0;
-                        // prefix sums of the run lengths from ballots: kRunLen
-                        // per active lane minus the shortfall d = kRunLen - len
-                        // (0..3) of the cells' last runs
-                        const int d = in ? kRunLen - len : 0;
-                        const uint64_t am = __ballot(in);
-                        const uint64_t d0 = __ballot(d & 1), d1 = __ballot(d & 2);
-                        const int lpre = kRunLen * __popcll(am & lt) - __popcll(d0 & lt) - 2 * __popcll(d1 & lt);
-                        const int lsum = kRunLen * __popcll(am) - __popcll(d0) - 2 * __popcll(d1);
-                        if (in) {
-                            const int pos = rpos + __popcll(am & lt);
-                            const int src = e.y + b * kRunLen;
-                            const int dst = perm_out ? beg + lbase + ppos + lpre : src;
-                            runs[beg + base + pos] = (dst << 2) | (len - 1);
-                            if (perm_out)
-                                for (int i = 0; i < len; ++i) perm_out[dst + i] = (uint32_t)(src + i);
-                        }
-                        rpos += __popcll(am);
-                        ppos += lsum;
-                        // the list is read ahead of every write (kept <= j0)
-                        const bool keep = in && left > kRunLen;
-                        const uint64_t km = __ballot(keep);
-                        if (keep) crowd[kept + __popcll(km & lt)] = e;
-                        kept += __popcll(km);
-                    }
-                    base += rpos;
-                    lbase += ppos;
-                    K = kept;
-                }
+            // wave w takes rounds nb0 + w, + NW, ... with its own list of the
+            // cells that still have a run in its next round (in cell order).
+            // Its first base follows from the rounds before it; after each
+            // round it adds the runs and particles of that round and of the
+            // NW - 1 rounds the other waves take, all counted on its list.
+            constexpr int NW = kRunsBuildThreads / 64;
+            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+            const uint64_t lt = (1ull << lane) - 1ull;
+            const int K = (int)total;
+            int *mylist = wl + w * kRunsMaxTileCells;
+            // runs and particles of one round b on a chunk of cells with counts n
+            auto round_counts = [&](bool in, int n, int b, int &r, int &q) {
+                const bool a = in && n > b * kRunLen;
+                const int d = a ? kRunLen - min(kRunLen, n - b * kRunLen) : 0;
+                const uint64_t am = __ballot(a), d0 = __ballot(d & 1), d1 = __ballot(d & 2);
+                r += __popcll(am);
+                q += kRunLen * __popcll(am) - __popcll(d0) - 2 * __popcll(d1);
+            };
+            int wb = base, wl0 = lbase, Kw = 0;
+            for (int j0 = 0; j0 < K; j0 += 64) {
+                const int j = j0 + lane;
+                const bool in = j < K;
+                const int n = in ? crowd[j].z : 0;
+                for (int k = 0; k < w; ++k) round_counts(in, n, nb0 + k, wb, wl0);
+                const bool keep = in && n > (nb0 + w) * kRunLen;
+                const uint64_t km = __ballot(keep);
+                if (keep) mylist[Kw + __popcll(km & lt)] = j;
+                Kw += __popcll(km);
             }
+            for (int b = nb0 + w; Kw > 0; b += NW) {
+                int kept = 0, rpos = 0, ppos = 0, radd = 0, padd = 0;
+                for (int j0 = 0; j0 < Kw; j0 += 64) {
+                    const int j = j0 + lane;
+                    const bool in = j < Kw;
+                    const int idx = in ? mylist[j] : 0;
+                    const int4 e = in ? crowd[idx] : make_int4(0, 0, 0, 0);
+                    const int left = e.z - b * kRunLen;
+                    const int len = in ? min(kRunLen, left) : 0;
+                    // prefix sums of the run lengths from ballots: kRunLen per
+                    // active lane minus the shortfall (0..3) of last runs
+                    const int d = in ? kRunLen - len : 0;
+                    const uint64_t am = __ballot(in);
+                    const uint64_t d0 = __ballot(d & 1), d1 = __ballot(d & 2);
+                    const int lpre = kRunLen * __popcll(am & lt) - __popcll(d0 & lt) - 2 * __popcll(d1 & lt);
+                    if (in) {
+                        const int pos = rpos + __popcll(am & lt);
+                        const int src = e.y + b * kRunLen;
+                        const int dst = perm_out ? beg + wl0 + ppos + lpre : src;
+                        runs[beg + wb + pos] = (dst << 2) | (len - 1);
+                        if (perm_out)
+                            for (int i = 0; i < len; ++i) perm_out[dst + i] = (uint32_t)(src + i);
+                    }
+                    rpos += __popcll(am);
+                    ppos += kRunLen * __popcll(am) - __popcll(d0) - 2 * __popcll(d1);
+                    for (int k = 1; k < NW; ++k) round_counts(in, e.z, b + k, radd, padd);
+                    // the list is read ahead of every write (kept <= j0)
+                    const bool keep = in && e.z > (b + NW) * kRunLen;
+                    const uint64_t km = __ballot(keep);
+                    if (keep) mylist[kept + __popcll(km & lt)] = idx;
+                    kept += __popcll(km);
+                }
+                wb += rpos + radd;
+                wl0 += ppos + padd;
+                Kw = kept;
+            }
+            base = (int)truns;
         }
         if (threadIdx.x == 0) runs[np + t] = base;
         __syncthreads();
