@@ -331,8 +331,9 @@ __global__ void k_rank_keys(uint32_t *keys, int np, const int32_t *cs, int cell_
 // (k_compose_perm then composes it with the sort's permutation).  The first
 // kRunsDense rounds (run index inside the cell) take one block scan each; the
 // cells with more runs (crowded cells of clumped particles, up to hundreds of
-// rounds) are then listed in cell order and one wave takes the remaining
-// rounds, dropping every cell from the list after its last run.
+// rounds) are then listed in cell order and the block's waves take the
+// remaining rounds in turn, each dropping a cell from its own list after the
+// cell's last run in that wave's rounds.
 constexpr int kRunsBuildThreads = 256;
 constexpr int kRunsDense = 8;
 static_assert(kRunLen == 4, "the crowded rounds' ballot prefix sums take run shortfalls of two bits");
