@@ -980,7 +980,7 @@ __device__ __forceinline__ void runs_unit(const ItemDesc &I, int t, int piece, i
         // and channel.  The next unit is claimed first, so the claim's
         // round trip overlaps the flush.
         __syncthreads();
-        if (threadIdx.x == 0) ctl[0] = (int)atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) ctl[0] = (int)atomicAdd(counter + (blockIdx.x + ctl[3]) % kQueues, 1u);
         pre = true;
         if (do_sums && threadIdx.x < 8 && S.sums[threadIdx.x] != 0.0) global_add(I.psum + threadIdx.x, S.sums[threadIdx.x]);
         {
@@ -1005,23 +1005,40 @@ __device__ __forceinline__ void runs_unit(const ItemDesc &I, int t, int piece, i
     }
 }
 
-// Claim of the run kernels' next work unit into ctl[0] (or the one claimed
-// before the last flush, pre): false when the launch's units are exhausted;
-// otherwise the unit's item, tile and piece, with t = -1 for an empty or
-// skipped slot.  Item k of the launch owns units [unit_begin + k * kRunsSplit,
-// + nunits + kRunsSplit); the sort lists an item's units largest first as
-// (tile, piece | npieces << 16).
+// Claim of the run kernels' next work unit.  The launch's unit slots are cut
+// into kQueues contiguous chunks (neighbouring tiles share a chunk), each with
+// its own counter; block b starts on chunk b % kQueues and moves to the next
+// chunk when its own is exhausted (qi chunks passed, mirrored in ctl[3] for
+// the claim issued before a flush).  Blocks are dispatched to the XCDs in
+// turn, so the blocks of one XCD mostly share a chunk and find its field
+// records in their L2; results do not depend on that placement.  The claim
+// goes into ctl[0] (or was issued before the last flush, pre): false when
+// every chunk is exhausted; otherwise the unit's item, tile and piece, with
+// t = -1 for an empty or skipped slot.  Item k of the launch owns slots
+// [unit_begin + k * kRunsSplit, + nunits + kRunsSplit); the sort lists an
+// item's units largest first as (tile, piece | npieces << 16).
+__device__ __forceinline__ int queue_lo(int q, int total) { return (int)((long long)total * q / kQueues); }
+
 __device__ __forceinline__ bool runs_claim(const ItemDesc *__restrict__ items, int nitems, int total_units,
-                                           unsigned *counter, int *errflags, int *ctl, bool &pre, int &iti, int &t,
-                                           int &piece, int &npieces)
+                                           unsigned *counter, int *errflags, int *ctl, bool &pre, int &qi, int &iti,
+                                           int &t, int &piece, int &npieces)
 {
     __syncthreads();
-    if (!pre && threadIdx.x == 0) ctl[0] = (int)atomicAdd(counter, 1u);
+    if (!pre && threadIdx.x == 0 && qi < kQueues)
+        ctl[0] = (int)atomicAdd(counter + (blockIdx.x + qi) % kQueues, 1u);
     __syncthreads();
     pre = false;
     t = -1;
-    const int g = __builtin_amdgcn_readfirstlane(ctl[0]);
-    if ((unsigned)g >= (unsigned)total_units) return false;
+    if (qi >= kQueues) return false;
+    const int q = (int)((blockIdx.x + qi) % kQueues);
+    const int qlo = queue_lo(q, total_units), qhi = queue_lo(q + 1, total_units);
+    const int g = qlo + __builtin_amdgcn_readfirstlane(ctl[0]);
+    if (g >= qhi) {
+        // this chunk is exhausted: the next one
+        ++qi;
+        if (threadIdx.x == 0) ctl[3] = qi;
+        return true;                                          // uniform
+    }
     iti = 0;
     while (iti + 1 < nitems && items[iti + 1].unit_begin + (iti + 1) * kRunsSplit <= g) ++iti;
     const ItemDesc &I = items[iti];
@@ -1034,9 +1051,10 @@ __device__ __forceinline__ bool runs_claim(const ItemDesc *__restrict__ items, i
     // never sorted (or its count changed since): latch it, leave it alone
     const bool stale = I.tile_start[0] != 0 || I.tile_start[I.ntiles] != I.np || (I.np > 0 && nu == 0);
     if (stale || local >= nu) {
-        // the rest of this item's units are empty: move the counter past them
+        // the rest of this item's slots in the chunk are empty: move the
+        // chunk's counter past them
         if (threadIdx.x == 0) {
-            atomicMax(counter, (unsigned)(ubeg + ucap));
+            atomicMax(counter + q, (unsigned)(min(ubeg + ucap, qhi) - qlo));
             if (stale) atomicOr(errflags, (int)ERR_UNSORTED);
         }
         return true;                                          // uniform
@@ -1048,6 +1066,20 @@ __device__ __forceinline__ bool runs_claim(const ItemDesc *__restrict__ items, i
     if ((unsigned)tt >= (unsigned)I.ntiles || npieces < 1 || piece >= npieces) return true;      // uniform
     t = tt;
     return true;
+}
+
+// The last block to finish resets the chunk counters for the next launch.
+__device__ __forceinline__ void release_queues(unsigned *counter)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned done = atomicAdd(counter + kQueues, 1u);
+        if (done == gridDim.x - 1) {
+            for (int q = 0; q < kQueues; ++q) atomicExch(counter + q, 0u);
+            atomicExch(counter + kQueues, 0u);
+        }
+    }
 }
 
 __device__ __forceinline__ void runs_latch(int err, int *errflags)
@@ -1071,14 +1103,16 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
     int *ctl = reinterpret_cast<int *>(smem_raw + lds_bytes - 16);
     int err = 0;
     bool pre = false;                      // uniform: ctl[0] already holds the next claim
+    int qi = 0;                            // uniform: chunks passed
+    if (threadIdx.x == 0) ctl[3] = 0;
     int iti = 0, t = -1, piece = 0, npieces = 1;
-    while (runs_claim(items, nitems, total_units, counter, errflags, ctl, pre, iti, t, piece, npieces)) {
+    while (runs_claim(items, nitems, total_units, counter, errflags, ctl, pre, qi, iti, t, piece, npieces)) {
         if (t < 0) continue;                                  // uniform
         runs_unit<PREC, SHAPE, DIM, KIND, HF, TS, CHS>(items[iti], t, piece, npieces, flags, lds_bytes, smem_raw,
                                                       counter, pre, err);
     }
     runs_latch(err, errflags);
-    release_counter(counter);
+    release_queues(counter);
 }
 
 // One persistent launch over the items of every species kind of a call: each
@@ -1093,8 +1127,10 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
     int *ctl = reinterpret_cast<int *>(smem_raw + lds_bytes - 16);
     int err = 0;
     bool pre = false;
+    int qi = 0;
+    if (threadIdx.x == 0) ctl[3] = 0;
     int iti = 0, t = -1, piece = 0, npieces = 1;
-    while (runs_claim(items, nitems, total_units, counter, errflags, ctl, pre, iti, t, piece, npieces)) {
+    while (runs_claim(items, nitems, total_units, counter, errflags, ctl, pre, qi, iti, t, piece, npieces)) {
         if (t < 0) continue;                                  // uniform
         const ItemDesc &I = items[iti];
         const int kind = __builtin_amdgcn_readfirstlane(I.kind);
@@ -1109,7 +1145,7 @@ __global__ __launch_bounds__(kRunsThreads) __attribute__((amdgpu_waves_per_eu(2,
                                                               counter, pre, err);
     }
     runs_latch(err, errflags);
-    release_counter(counter);
+    release_queues(counter);
 }
 
 // ---------------------------------------------------------------------------

@@ -46,18 +46,18 @@ hipError_t launch_step(Ctx *c, const ItemDesc *table, const std::vector<ItemDesc
         hipError_t e = hipErrorInvalidConfiguration;
         if (c->d.algo == PL_ALGO_RUNS && push && deposit && host[i0].kind != PL_TRACER)
             e = c->d.prec == PL_F64 ? launch_runs_f64(c, table + i0, host.data() + i0, i1 - i0, units, sf,
-                                                      c->counters + 2 * group)
+                                                      c->counters + kCounterStride * group)
                                     : launch_runs_f32(c, table + i0, host.data() + i0, i1 - i0, units, sf,
-                                                      c->counters + 2 * group);
+                                                      c->counters + kCounterStride * group);
         if (e == hipErrorInvalidConfiguration && c->d.algo == PL_ALGO_RUNS && push && deposit &&
             host[i0].kind != PL_TRACER)
             c->stats[5]++;
         if (e == hipErrorInvalidConfiguration)
             e = c->d.prec == PL_F64
                     ? launch_group_f64(c, table + i0, host.data() + i0, i1 - i0, units, sf, push, deposit,
-                                       c->counters + 2 * group)
+                                       c->counters + kCounterStride * group)
                     : launch_group_f32(c, table + i0, host.data() + i0, i1 - i0, units, sf, push, deposit,
-                                       c->counters + 2 * group);
+                                       c->counters + kCounterStride * group);
         if (e != hipSuccess) return e;
         i0 = i1;
         ++group;

@@ -530,7 +530,7 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d)
     const size_t nblocks = (np + 8191) / 8192;
     c->hist_cap = (int64_t)(256 * nblocks + 1024);
     bool ok = hipMalloc(&c->table, mi * sizeof(ItemDesc)) == hipSuccess &&
-              hipMalloc(&c->counters, 64 * sizeof(unsigned)) == hipSuccess &&
+              hipMalloc(&c->counters, kCounterSlots * sizeof(unsigned)) == hipSuccess &&
               hipMalloc(&c->errflags, 4 * sizeof(int)) == hipSuccess &&
               hipMalloc(&c->sums, 16 * mi * sizeof(double)) == hipSuccess &&
               hipMalloc(&c->hist, (size_t)c->hist_cap * sizeof(uint32_t)) == hipSuccess &&
@@ -549,7 +549,7 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d)
         free_ctx(c);
         return PL_ENOMEM;
     }
-    if (hipMemset(c->counters, 0, 64 * sizeof(unsigned)) != hipSuccess ||
+    if (hipMemset(c->counters, 0, kCounterSlots * sizeof(unsigned)) != hipSuccess ||
         hipMemset(c->errflags, 0, 4 * sizeof(int)) != hipSuccess ||
         hipMemset(c->sums, 0, 16 * mi * sizeof(double)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         free_ctx(c);

@@ -16,6 +16,10 @@ constexpr int kMaxN = 1 << kCellBits;
 constexpr int kRunLen = 4;           // particles per run of the run table (PL_ALGO_RUNS)
 constexpr int kRunsMaxTileCells = 1024;
 constexpr int kRunsSplit = PL_RUNS_SPLIT_UNITS;   // work units beyond one per tile
+constexpr int kQueues = 8;          // run kernels: chunks of the unit slots, one counter each
+constexpr int kCounterStride = 16;  // counters per launch stage (kQueues + 1 used by the run kernels)
+constexpr int kCounterSlots = 4 * kCounterStride;   // one stage per species kind, plus one
+static_assert(kQueues + 1 <= kCounterStride, "a run-kernel stage needs kQueues + 1 counters");
 constexpr int kRunsMinPiece = 1024;               // smallest run count worth a split
 
 // Run table of an item (PL_ALGO_RUNS), offsets from runs[0]: unit g is the
@@ -116,7 +120,7 @@ struct Ctx {
 
     // device scratch
     ItemDesc *table = nullptr;       // max_items descriptors for non-graph calls
-    unsigned *counters = nullptr;    // work counters: 2 per launch stage
+    unsigned *counters = nullptr;    // work counters: kCounterStride per launch stage
     int *errflags = nullptr;         // latched error bits
     double *sums = nullptr;          // max_items * 16
     uint32_t *keys[2] = {nullptr, nullptr};
