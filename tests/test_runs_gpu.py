@@ -146,11 +146,13 @@ def relaid_runs(exp, tstart, npart, ntiles):
 def test_runs_table_exact(mods, prec, key):
     oracle, driver, inputs, B = mods
     kmode = B.PL_KEY_TILE_CELL if key == "cell" else B.PL_KEY_TILE_RUN
-    # 40 per cell: most cells of every 8^3 tile hold more than eight runs (the
-    # run-table build takes the rounds beyond eight with one wave)
+    # 40 per cell: most cells of every tile hold more than eight runs (the
+    # run-table build shares the rounds beyond eight among its waves); the
+    # 16x8x8 tile has the largest cell count a tile may have (1024)
     for n, npart, tile in ((32, 8 * 32 ** 3 - 37, (8, 8, 8)), (16, 1, (4, 4, 4)), (16, 3001, (16, 8, 2)),
-                           (16, 20000, (4, 4, 4)), (16, 40 * 16 ** 3 + 5, (8, 8, 8)), (32, -1, (4, 4, 4)),
-                           (32, -2, (4, 4, 4)), (32, -2, (8, 8, 8))):
+                           (16, 20000, (4, 4, 4)), (16, 40 * 16 ** 3 + 5, (8, 8, 8)),
+                           (16, 40 * 16 ** 3 + 5, (16, 8, 8)), (32, -1, (4, 4, 4)), (32, -2, (4, 4, 4)),
+                           (32, -2, (8, 8, 8))):
         say(f"[runs] run table {prec} key {key} n={n} np={npart} tile={tile}")
         split = npart < 0 and tile == (4, 4, 4)
         if npart < 0:
