@@ -156,6 +156,54 @@ def test_unsorted_item_is_latched(mods, prec, algo):
     run.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_unsorted_item_in_batch(mods, prec):
+    """In a batched run-based step, an item whose count changed since its sort
+    is latched and left as it was, while every other item advances exactly
+    (bit for bit) as in the same step with all items sorted: its unit slots are
+    skipped chunk by chunk without holding up the others."""
+    oracle, driver, inputs, B = mods
+    from tests.test_parity_gpu import _small_batch
+    say(f"[variants] unsorted item inside a batch: {prec}")
+    wl = _small_batch(inputs)
+    p = B.PL_F64 if prec == "f64" else B.PL_F32_OFFSET
+
+    def snap(run, i):
+        raw = run.raw(i)
+        ids = raw["id"].astype(np.int64)
+        return {k: np.stack(v) if isinstance(v, list) else v.copy() for k, v in raw.items()
+                if k in ("cell", "x", "u")}, ids
+
+    ref = driver.Run(wl, prec=p, algo=B.PL_ALGO_RUNS)
+    ref.sort()
+    ref.step()
+    assert ref.sync() == B.PL_OK
+    want = [snap(ref, i) for i in range(len(wl.items))]
+    ref.close()
+
+    run = driver.Run(wl, prec=p, algo=B.PL_ALGO_RUNS)
+    run.sort()
+    k = max(range(len(wl.items)), key=lambda i: run.items[i].p.n if wl.species[wl.items[i].species].kind != "tracer" else -1)
+    before = snap(run, k)
+    n = run.items[k].p.n
+    run.items[k].p.n = n - 3
+    run.step()
+    assert run.sync() == B.PL_ENOTSORTED
+    run.items[k].p.n = n
+    after = snap(run, k)
+    for key in before[0]:
+        assert np.array_equal(before[0][key], after[0][key]), key
+    for i in range(len(wl.items)):
+        if i == k:
+            continue
+        got, gid = snap(run, i)
+        ref_state, rid = want[i]
+        assert np.array_equal(gid, rid), i
+        for key in got:
+            assert np.array_equal(got[key], ref_state[key]), (i, key)
+    run.close()
+
+
 def test_force_deposit_after_sort_rejected(mods):
     """p.fp is written in the particle order of a gather_push and a sort does
     not move it: a deposit of F between a sort and the next gather_push is
