@@ -242,3 +242,48 @@ def test_open_box_outflow_and_injection(mods):
     assert B.pl_part_inject(run.ctx, run.items[0], big.shape[1], [0, 0, 0], [0, 0, 0], cap=2 * npart,
                             check=False) == B.PL_EINVAL
     run.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_boundary_edge_cases(mods, prec):
+    """No open dimension: nothing removed, every array untouched.  Every
+    particle inside the ghost layers of an open dimension: all removed, and the
+    emptied item sorts and steps.  An empty item: nothing removed."""
+    oracle, driver, inputs, B = mods
+    n = 16
+    p = B.PL_F64 if prec == "f64" else B.PL_F32_OFFSET
+    say(f"[lp] boundary edge cases {prec}")
+    rng = np.random.default_rng(77)
+    # nothing open
+    wl = inputs.turbulent_box(n=n, npart=777, steps=1)
+    run = driver.Run(wl, prec=p, algo=B.PL_ALGO_TILED, tile=(4, 4, 4))
+    run.sort()
+    before = {k: (np.stack(v) if isinstance(v, list) else v).copy() for k, v in run.raw(0).items()}
+    assert run.boundary((0, 0, 0), 2) == [0]
+    assert run.items[0].p.n == 777
+    after = run.raw(0)
+    for k, v in before.items():
+        assert np.array_equal(v, np.stack(after[k]) if isinstance(after[k], list) else after[k]), k
+    run.step(flags=0)
+    assert run.sync() == B.PL_OK
+    run.close()
+    # every particle in the ghost layers of x (x < 2 or x >= n - 2)
+    npart = 500
+    x = rng.random((3, npart)) * n
+    x[0] = np.where(rng.random(npart) < 0.5, rng.random(npart) * 2.0, n - 2.0 + rng.random(npart) * 1.999)
+    wl.items[0].particles = inputs.make_particles(x, np.zeros((3, npart)))
+    run = driver.Run(wl, prec=p, algo=B.PL_ALGO_TILED, tile=(4, 4, 4))
+    run.sort()
+    assert run.boundary((1, 0, 0), 2) == [npart]
+    assert run.items[0].p.n == 0
+    run.sort()
+    run.step(flags=0)
+    assert run.sync() == B.PL_OK
+    run.close()
+    # an empty item
+    wl.items[0].particles = inputs.make_particles(np.zeros((3, 0)), np.zeros((3, 0)))
+    run = driver.Run(wl, prec=p, algo=B.PL_ALGO_TILED, tile=(4, 4, 4))
+    run.sort()
+    assert run.boundary((1, 1, 1), 2) == [0]
+    assert run.items[0].p.n == 0
+    run.close()
