@@ -26,11 +26,32 @@ constexpr int kPerWave = 1024;                       // elements per wave per bl
 constexpr int kPerBlock = kSortWaves * kPerWave;     // elements per block
 constexpr int kScanBlocks = 512;
 
+// Digit counts of the 64 keys from e0 (those below end) added to cnt: the
+// first lane of every run of equal digits adds the run's length.  All lanes
+// of the wave take part.
+__device__ __forceinline__ void count_runs(const uint32_t *keys, int e0, int end, int shift, uint32_t mask,
+                                           uint32_t *cnt)
+{
+    const int lane = threadIdx.x & 63;
+    const int e = e0 + lane;
+    const bool v = e < end;
+    const uint32_t d = v ? (keys[e] >> shift) & mask : ~0u;
+    const uint32_t prev = __shfl_up(d, 1, 64);
+    const bool head = v && (lane == 0 || prev != d);
+    const uint64_t hm = __ballot(head);
+    if (head) {
+        const uint64_t later = hm & ~((2ull << lane) - 1ull);     // heads after this lane
+        const int stop = later ? __builtin_ctzll(later) : min(64, end - e0);
+        atomicAdd(&cnt[d], (uint32_t)(stop - lane));
+    }
+}
+
 __global__ void k_keys(SortArgs a, uint32_t *keys)
 {
     const int tx = a.tile[0], ty = a.tile[1], tz = a.tile[2];
     const int ntx = a.n[0] / tx, nty = a.n[1] / ty;
     const int per_tile = tx * ty * tz;
+    const bool p2 = ((tx & (tx - 1)) | (ty & (ty - 1)) | (tz & (tz - 1))) == 0;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < a.np; p += gridDim.x * blockDim.x) {
         int c[3] = {0, 0, 0};
         if (a.prec == PL_F32_OFFSET) {
@@ -49,10 +70,24 @@ __global__ void k_keys(SortArgs a, uint32_t *keys)
                 c[d] = (int)floor(v);
             }
         }
-        int t = c[0] / tx + ntx * (c[1] / ty + nty * (c[2] / tz));
+        // power-of-two tile sides (the usual case) divide by shifts
+        int q[3], r[3];
+        const int td[3] = {tx, ty, tz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (p2) {
+                const int lg = __builtin_ctz((unsigned)td[d]);
+                q[d] = c[d] >> lg;
+                r[d] = c[d] & (td[d] - 1);
+            } else {
+                q[d] = c[d] / td[d];
+                r[d] = c[d] % td[d];
+            }
+        }
+        int t = q[0] + ntx * (q[1] + nty * q[2]);
         uint32_t key = (uint32_t)t;
         if (a.key_mode == PL_KEY_TILE_CELL || a.key_mode == PL_KEY_TILE_RUN) {
-            int yy = c[1] % ty;
+            int yy = r[1];
             // run order: rows taken as 0, 2, 4, 6, 1, 3, 5, 7 within every group
             // of eight (0, 2, 1, 3 within groups of four), so that the lanes
             // served together by one LDS access hold rows of one parity and
@@ -61,26 +96,31 @@ __global__ void k_keys(SortArgs a, uint32_t *keys)
                 yy = (yy & ~7) | ((yy & 1) << 2) | ((yy >> 1) & 3);
             else if (a.key_mode == PL_KEY_TILE_RUN && (ty & 3) == 0)
                 yy = (yy & ~3) | ((yy & 1) << 1) | ((yy >> 1) & 1);
-            int loc = c[0] % tx + tx * (yy + ty * (c[2] % tz));
+            int loc = r[0] + tx * (yy + ty * r[2]);
             key = (uint32_t)t * (uint32_t)per_tile + (uint32_t)loc;
         }
         keys[p] = key;
     }
 }
 
-// Per-block digit histogram, stored digit-major: hist[d * nblocks + b].
-__global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t *keys, int np, int shift, int nblocks,
-                                                       uint32_t *hist)
+// Per-block digit histogram of dbits-bit digits, stored digit-major:
+// hist[d * nblocks + b].  Equal digits in consecutive lanes (the keys are
+// mostly in order after the first sort) count with one LDS atomic per run.
+__global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t *keys, int np, int shift, int dbits,
+                                                       int nblocks, uint32_t *hist)
 {
-    __shared__ uint32_t h[256];
-    for (int d = threadIdx.x; d < 256; d += blockDim.x) h[d] = 0;
+    __shared__ uint32_t h[1 << kMaxDigitBits];
+    const int nd = 1 << dbits;
+    const uint32_t mask = (uint32_t)nd - 1u;
+    for (int d = threadIdx.x; d < nd; d += blockDim.x) h[d] = 0;
     __syncthreads();
-    int beg = blockIdx.x * kPerBlock;
-    int end = min(np, beg + kPerBlock);
-    for (int e = beg + threadIdx.x; e < end; e += blockDim.x)
-        atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+    const int lane = threadIdx.x & 63;
+    const int beg = blockIdx.x * kPerBlock;
+    const int end = min(np, beg + kPerBlock);
+    for (int e0 = beg + (int)threadIdx.x - lane; e0 < end; e0 += blockDim.x)       // uniform per wave
+        count_runs(keys, e0, end, shift, mask, h);
     __syncthreads();
-    for (int d = threadIdx.x; d < 256; d += blockDim.x) hist[(size_t)d * nblocks + blockIdx.x] = h[d];
+    for (int d = threadIdx.x; d < nd; d += blockDim.x) hist[(size_t)d * nblocks + blockIdx.x] = h[d];
 }
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total)
@@ -150,26 +190,30 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *in, long m, 
     }
 }
 
-// Stable scatter of one radix pass.  idx_in == nullptr means identity
-// (first pass).
+// Stable scatter of one radix pass of dbits-bit digits (per-wave digit
+// cursors in dynamic LDS: kSortWaves << dbits words).  idx_in == nullptr
+// means identity (first pass).
 __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t *keys_in, const uint32_t *idx_in,
                                                           uint32_t *keys_out, uint32_t *idx_out, int np,
-                                                          int shift, int nblocks, const uint32_t *offs)
+                                                          int shift, int dbits, int nblocks, const uint32_t *offs)
 {
-    __shared__ uint32_t wc[kSortWaves][256];
+    extern __shared__ uint32_t wcs[];
+    const int nd = 1 << dbits;
+    const uint32_t mask = (uint32_t)nd - 1u;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int e = threadIdx.x; e < kSortWaves * 256; e += blockDim.x) (&wc[0][0])[e] = 0;
+    uint32_t *wc = wcs + wv * nd;                     // this wave's cursors
+    for (int e = threadIdx.x; e < kSortWaves * nd; e += blockDim.x) wcs[e] = 0;
     __syncthreads();
     const int bbeg = blockIdx.x * kPerBlock;
     const int wbeg = bbeg + wv * kPerWave;
     const int wend = min(np, wbeg + kPerWave);
-    for (int e = wbeg + lane; e < wend; e += 64) atomicAdd(&wc[wv][(keys_in[e] >> shift) & 255u], 1u);
+    for (int e0 = wbeg; e0 < wend; e0 += 64) count_runs(keys_in, e0, wend, shift, mask, wc);
     __syncthreads();
-    for (int d = threadIdx.x; d < 256; d += blockDim.x) {
+    for (int d = threadIdx.x; d < nd; d += blockDim.x) {
         uint32_t run = offs[(size_t)d * nblocks + blockIdx.x];
         for (int w = 0; w < kSortWaves; ++w) {
-            uint32_t t = wc[w][d];
-            wc[w][d] = run;
+            uint32_t t = wcs[w * nd + d];
+            wcs[w * nd + d] = run;
             run += t;
         }
     }
@@ -180,26 +224,25 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t *keys_i
         bool valid = e < wend;
         uint32_t k = valid ? keys_in[e] : 0u;
         uint32_t id = valid ? (idx_in ? idx_in[e] : (uint32_t)e) : 0u;
-        uint32_t d = (k >> shift) & 255u;
+        uint32_t d = (k >> shift) & mask;
         uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < dbits; ++b) {
             uint64_t m = __ballot(valid && ((d >> b) & 1u));
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
         if (valid) {
             uint32_t rank = (uint32_t)__popcll(peers & lt);
-            uint32_t dst = wc[wv][d] + rank;
+            uint32_t dst = wc[d] + rank;
             keys_out[dst] = k;
             idx_out[dst] = id;
         }
-        // make every lane's read of wc[wv][d] happen before the update
+        // make every lane's read of wc[d] happen before the update
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         if (valid) {
             // highest lane of each peer group advances its digit's cursor
             uint64_t higher = peers & ~(lt | (1ull << lane));
-            if (higher == 0) wc[wv][d] += (uint32_t)__popcll(peers);
+            if (higher == 0) wc[d] += (uint32_t)__popcll(peers);
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -208,7 +251,8 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint32_t *keys_i
 
 // Every SoA array of an item moved by one permutation in one pass: the
 // permutation is read once, and all of a position's loads are in flight
-// before its stores.
+// before its stores.  With perm2 the source of position r is
+// perm2[perm[r]] (run order: new position -> sorted position -> source).
 struct PermArrays {
     const void *src[SortArgs::kMaxArrays];
     void *dst[SortArgs::kMaxArrays];
@@ -216,14 +260,19 @@ struct PermArrays {
     int n;
 };
 
-__global__ void k_permute_all(const uint32_t *__restrict__ perm, int np, PermArrays pa)
+__global__ void k_permute_all(const uint32_t *__restrict__ perm, const uint32_t *__restrict__ perm2, int np,
+                              PermArrays pa)
 {
     // two positions per iteration, every load of both issued before any store
     const int stride = gridDim.x * blockDim.x;
     for (int r0 = blockIdx.x * blockDim.x + threadIdx.x; r0 < np; r0 += 2 * stride) {
         const int r1 = r0 + stride;
         const bool two = r1 < np;
-        const uint32_t q0 = perm[r0], q1 = two ? perm[r1] : q0;
+        uint32_t q0 = perm[r0], q1 = two ? perm[r1] : q0;
+        if (perm2) {
+            q0 = perm2[q0];
+            q1 = perm2[q1];
+        }
         unsigned long long v0[SortArgs::kMaxArrays], v1[SortArgs::kMaxArrays];
 #pragma unroll
         for (int k = 0; k < SortArgs::kMaxArrays; ++k) {
@@ -253,13 +302,15 @@ __global__ void k_permute_all(const uint32_t *__restrict__ perm, int np, PermArr
 }
 
 // Spectral rows (nb float64 per particle, particle-major): destination row r
-// takes source row perm[r]; one wave per row.
-__global__ __launch_bounds__(256) void k_permute_rows(const uint32_t *perm, int np, int nb, const double *src0,
-                                                      double *dst0, const double *src1, double *dst1)
+// takes source row perm[r] (perm2[perm[r]] with perm2); one wave per row.
+__global__ __launch_bounds__(256) void k_permute_rows(const uint32_t *perm, const uint32_t *perm2, int np, int nb,
+                                                      const double *src0, double *dst0, const double *src1,
+                                                      double *dst1)
 {
     const int lane = threadIdx.x & 63;
     for (int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < np; r += (gridDim.x * blockDim.x) >> 6) {
-        const long s = (long)perm[r] * nb, d = (long)r * nb;
+        const uint32_t q = perm2 ? perm2[perm[r]] : perm[r];
+        const long s = (long)q * nb, d = (long)r * nb;
         for (int i = lane; i < nb; i += 64) {
             dst0[d + i] = src0[s + i];
             dst1[d + i] = src1[s + i];
@@ -267,12 +318,12 @@ __global__ __launch_bounds__(256) void k_permute_rows(const uint32_t *perm, int 
     }
 }
 
-static void permute_arrays(Ctx *c, const SortArgs &a, const uint32_t *perm, int grid)
+static void permute_arrays(Ctx *c, const SortArgs &a, const uint32_t *perm, const uint32_t *perm2, int grid)
 {
     if (a.nb > 0) {
         const int g = std::max(1, std::min((a.np + 3) / 4, 64 * c->num_cu));
-        hipLaunchKernelGGL(k_permute_rows, dim3(g), dim3(256), 0, c->stream, perm, a.np, a.nb, a.rsrc[0], a.rdst[0],
-                           a.rsrc[1], a.rdst[1]);
+        hipLaunchKernelGGL(k_permute_rows, dim3(g), dim3(256), 0, c->stream, perm, perm2, a.np, a.nb, a.rsrc[0],
+                           a.rdst[0], a.rsrc[1], a.rdst[1]);
         c->stats[0]++;
     }
     PermArrays pa;
@@ -283,7 +334,7 @@ static void permute_arrays(Ctx *c, const SortArgs &a, const uint32_t *perm, int 
         pa.dst[k] = a.dst[k];
         if (a.esize[k] == 8) pa.wide |= 1 << k;
     }
-    hipLaunchKernelGGL(k_permute_all, dim3(grid), dim3(256), 0, c->stream, perm, a.np, pa);
+    hipLaunchKernelGGL(k_permute_all, dim3(grid), dim3(256), 0, c->stream, perm, perm2, a.np, pa);
     c->stats[0]++;
 }
 
@@ -309,13 +360,14 @@ __global__ void k_cell_start(const uint32_t *keys, int np, int32_t *cs)
 // Rank-interleaved key of sorted position r: its rank among the particles of
 // its cell (positions are in stable order, so this is the number of earlier
 // particles of the same cell), capped at 2^rank_bits - 1, between tile and cell.
-__global__ void k_rank_keys(uint32_t *keys, int np, const int32_t *cs, int cell_bits, int rank_bits)
+// The input key is tile * per_tile + cell in tile; per_tile <= 2^cell_bits.
+__global__ void k_rank_keys(uint32_t *keys, int np, const int32_t *cs, int per_tile, int cell_bits, int rank_bits)
 {
-    const uint32_t cmask = (1u << cell_bits) - 1u, rmax = (1u << rank_bits) - 1u;
+    const uint32_t rmax = (1u << rank_bits) - 1u, pt = (uint32_t)per_tile;
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < np; r += gridDim.x * blockDim.x) {
         uint32_t k = keys[r];
         uint32_t rank = min((uint32_t)(r - cs[k]), rmax);
-        uint32_t tile = k >> cell_bits, local = k & cmask;
+        uint32_t tile = k / pt, local = k - tile * pt;
         keys[r] = (tile << (rank_bits + cell_bits)) | (rank << cell_bits) | local;
     }
 }
@@ -328,7 +380,7 @@ __global__ void k_rank_keys(uint32_t *keys, int np, const int32_t *cs, int cell_
 // the tile's run count goes to runs[np + t].  With perm_out (run order) the
 // runs are laid out one after another in table order from tile_start[t]: the
 // entries hold those positions, and perm_out[new position] = sorted position
-// (k_compose_perm then composes it with the sort's permutation).  The first
+// (the permute pass composes it with the sort's permutation).  The first
 // kRunsDense rounds (run index inside the cell) take one block scan each; the
 // cells with more runs (crowded cells of clumped particles, up to hundreds of
 // rounds) are then listed in cell order and the block's waves take the
@@ -521,13 +573,6 @@ __global__ __launch_bounds__(kRunsBuildThreads) void k_runs_build(const uint32_t
     }
 }
 
-// perm[q] = perm_in[perm[q]]: new position -> sorted position -> source
-// index.
-__global__ void k_compose_perm(uint32_t *perm, const uint32_t *perm_in, int np)
-{
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < np; q += gridDim.x * blockDim.x) perm[q] = perm_in[perm[q]];
-}
-
 // Work units of the run-based kernel (one block).  With P = max(ceil(total
 // runs / kRunsSplit), kRunsMinPiece), a tile of c runs becomes ceil(c / P)
 // pieces (an empty tile none), so at most ntiles + kRunsSplit units exist.
@@ -640,24 +685,31 @@ static int bits_for(uint64_t count)
 
 // LSD radix passes over the low `bits` bits of keys[src] with indices idx[src]
 // (identity when `identity`); returns the buffer index holding the result.
+// Digits of kMaxDigitBits bits, the last pass taking only the bits left.
+// (Wider digits, 11 bits in two passes for 21-bit keys, were slower: the
+// per-block digit tables cost more than the pass they save.)
 static int radix_passes(Ctx *c, int np, int src, bool identity, int bits)
 {
     hipStream_t s = c->stream;
-    const int npass = std::max(1, (bits + 7) / 8);
     const int nblocks = (np + kPerBlock - 1) / kPerBlock;
-    const long m = 256L * nblocks;
-    const long seg = (m + kScanBlocks - 1) / kScanBlocks;
-    const int nparts = (int)((m + seg - 1) / seg);
-    uint32_t *part = c->hist_scan + m;
+    bits = std::max(bits, 1);
+    const int width = kMaxDigitBits;
+    const int npass = (bits + width - 1) / width;
     for (int pass = 0; pass < npass; ++pass) {
-        int shift = 8 * pass;
-        hipLaunchKernelGGL(k_hist, dim3(nblocks), dim3(kSortThreads), 0, s, c->keys[src], np, shift, nblocks, c->hist);
+        const int shift = width * pass;
+        const int dbits = std::min(width, bits - shift);
+        const long m = (long)nblocks << dbits;
+        const long seg = (m + kScanBlocks - 1) / kScanBlocks;
+        const int nparts = (int)((m + seg - 1) / seg);
+        uint32_t *part = c->hist_scan + m;
+        hipLaunchKernelGGL(k_hist, dim3(nblocks), dim3(kSortThreads), 0, s, c->keys[src], np, shift, dbits, nblocks,
+                           c->hist);
         hipLaunchKernelGGL(k_scan_reduce, dim3(nparts), dim3(256), 0, s, c->hist, m, seg, part);
         hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanBlocks), 0, s, part, nparts);
         hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(256), 0, s, c->hist, m, seg, part, c->hist_scan);
-        hipLaunchKernelGGL(k_scatter, dim3(nblocks), dim3(kSortThreads), 0, s, c->keys[src],
-                           (identity && pass == 0) ? (const uint32_t *)nullptr : c->idx[src], c->keys[1 - src],
-                           c->idx[1 - src], np, shift, nblocks, c->hist_scan);
+        hipLaunchKernelGGL(k_scatter, dim3(nblocks), dim3(kSortThreads), (size_t)(kSortWaves << dbits) * 4, s,
+                           c->keys[src], (identity && pass == 0) ? (const uint32_t *)nullptr : c->idx[src],
+                           c->keys[1 - src], c->idx[1 - src], np, shift, dbits, nblocks, c->hist_scan);
         c->stats[0] += 5;
         src = 1 - src;
     }
@@ -692,7 +744,8 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
         const int cb = bits_for((uint64_t)per_tile_cells), tb = bits_for((uint64_t)a.ntiles);
         const int rb = std::min(10, 32 - tb - cb);
         hipLaunchKernelGGL(k_cell_start, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, c->cell_start);
-        hipLaunchKernelGGL(k_rank_keys, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, c->cell_start, cb, rb);
+        hipLaunchKernelGGL(k_rank_keys, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, c->cell_start,
+                           per_tile_cells, cb, rb);
         src = radix_passes(c, a.np, src, false, tb + rb + cb);
         shift = rb + cb;
         c->stats[0] += 3;
@@ -711,14 +764,12 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
         // one block per tile: a crowded tile's rounds do not hold up others
         hipLaunchKernelGGL(k_runs_build, dim3(std::max(a.ntiles, 1)), dim3(kRunsBuildThreads), 0, s,
                            c->keys[src], a.np, per_tile_cells, a.ntiles, a.tile_start, a.runs, c->idx[1 - src]);
-        hipLaunchKernelGGL(k_compose_perm, dim3(grid_e), dim3(256), 0, s, c->idx[1 - src],
-                           (const uint32_t *)c->idx[src], a.np);
-        permute_arrays(c, a, c->idx[1 - src], grid_e);
+        permute_arrays(c, a, c->idx[1 - src], c->idx[src], grid_e);
         hipLaunchKernelGGL(k_unit_list, dim3(1), dim3(kOrderThreads), 0, s, a.runs, a.np, a.ntiles);
-        c->stats[0] += 4;
+        c->stats[0] += 3;
         return hipGetLastError();
     }
-    permute_arrays(c, a, c->idx[src], grid_e);
+    permute_arrays(c, a, c->idx[src], nullptr, grid_e);
     hipLaunchKernelGGL(k_tile_start, dim3(grid_e), dim3(256), 0, s, c->keys[src], a.np, shift, div, a.ntiles,
                        a.tile_start);
     c->stats[0]++;
@@ -740,7 +791,7 @@ hipError_t launch_sort(Ctx *c, const SortArgs &a)
 // ---------------------------------------------------------------------------
 
 constexpr int64_t kNaNp = PL_NOALLOC_MAX_NP;
-constexpr int64_t kNaHist = 256 * ((kNaNp + kPerBlock - 1) / kPerBlock) + 1024;
+constexpr int64_t kNaHist = (((kNaNp + kPerBlock - 1) / kPerBlock) << kMaxDigitBits) + 1024;
 constexpr size_t kNaBytes = (size_t)(4 * kNaNp + 2 * kNaHist) * sizeof(uint32_t);
 
 static __device__ __align__(256) unsigned char scratch[kNaBytes];

@@ -528,7 +528,7 @@ pl_status pl_part_init(pl_ctx **out, const pl_init_desc *d)
     const size_t mi = (size_t)d->max_items;
     const size_t np = (size_t)std::max<int64_t>(d->max_np, 1);
     const size_t nblocks = (np + 8191) / 8192;
-    c->hist_cap = (int64_t)(256 * nblocks + 1024);
+    c->hist_cap = (int64_t)((nblocks << kMaxDigitBits) + 1024);    // digit-major counts of one radix pass
     bool ok = hipMalloc(&c->table, mi * sizeof(ItemDesc)) == hipSuccess &&
               hipMalloc(&c->counters, kCounterSlots * sizeof(unsigned)) == hipSuccess &&
               hipMalloc(&c->errflags, 4 * sizeof(int)) == hipSuccess &&

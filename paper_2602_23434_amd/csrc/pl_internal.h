@@ -13,6 +13,7 @@ namespace pl {
 constexpr int kMaxCh = 8;            // rho, J0, J1, J2, F0, F1, F2, eng
 constexpr int kCellBits = 10;        // packed cell: 10 bits per dimension
 constexpr int kMaxN = 1 << kCellBits;
+constexpr int kMaxDigitBits = 8;     // radix digit of the sort (256 counters per block and wave)
 constexpr int kRunLen = 4;           // particles per run of the run table (PL_ALGO_RUNS)
 constexpr int kRunsMaxTileCells = 1024;
 constexpr int kRunsSplit = PL_RUNS_SPLIT_UNITS;   // work units beyond one per tile

@@ -201,6 +201,41 @@ def test_sort_bitexact(mods, prec, key_mode):
         run.close()
 
 
+@pytest.mark.parametrize("key_mode", [1, 2])
+def test_sort_bitexact_wide_keys(mods, key_mode):
+    """Keys of 21 and 31 bits (128^3 box, 8^3 tiles: three and four radix
+    passes, the last one narrower) and a tile whose sides are not powers of
+    two (the rank-interleaved key splits tile and cell by division): the
+    permutation and the tile offsets are the oracle's, bit for bit."""
+    oracle, driver, inputs, B = mods
+    say(f"[parity] sort with wide keys, key_mode {key_mode}")
+    for n, npart, tile in ((128, (1 << 18) + 3, (8, 8, 8)), (48, 48 ** 3 + 7, (6, 4, 3))):
+        wl = inputs.turbulent_box(n=n, npart=npart, steps=0)
+        run = driver.Run(wl, prec=B.PL_F64, algo=B.PL_ALGO_TILED, key_mode=key_mode, tile=tile)
+        run.sort()
+        assert run.sync() == B.PL_OK
+        raw = run.raw(0)
+        bx = wl.boxes[0].n
+        cells = oracle.cells_of_positions(3, bx, wl.items[0].particles.x)
+        if key_mode == 2:
+            keys, rb = oracle.rank_keys(3, bx, tile, cells)
+        else:
+            keys = np.array([oracle.tile_key(3, bx, tile, key_mode, *cells[:, q]) for q in range(npart)],
+                            dtype=np.uint32)
+        say(f"  n {n} tile {tile}: keys up to {int(keys.max()).bit_length()} bits")
+        perm = oracle.stable_sort_perm(keys)
+        assert np.array_equal(raw["id"].astype(np.int64), perm)
+        ntiles = (n // tile[0]) * (n // tile[1]) * (n // tile[2])
+        per_tile = tile[0] * tile[1] * tile[2]
+        if key_mode == 2:
+            tkeys = keys[perm] >> (rb + int(per_tile - 1).bit_length())
+        else:
+            tkeys = keys[perm] // per_tile
+        expect = np.searchsorted(tkeys, np.arange(ntiles + 1), side="left")
+        assert np.array_equal(raw["tile_start"][: ntiles + 1], expect)
+        run.close()
+
+
 def test_sort_invariance(mods):
     """The per-particle state does not depend on tile size, key mode or sort
     cadence, bit for bit (the push of a particle reads only fields)."""
