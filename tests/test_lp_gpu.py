@@ -84,16 +84,22 @@ def test_spectra_vs_oracle(mods, prec, shape):
     run.close()
 
 
-def test_spectra_move_with_sort_and_push(mods):
+@pytest.mark.parametrize("algo", ["tiled", "runs"])
+def test_spectra_move_with_sort_and_push(mods, algo):
     """The paper's particle step, two RK stages then the spectral update
     (Table 1 order), with a sort every 2 steps: the spectral rows travel
-    with their particles through the sort, so per id they match the
-    oracle's."""
+    with their particles through the sort (in run order through the run
+    table's permutation composed with the tile+cell one), so per id they
+    match the oracle's."""
     oracle, driver, inputs, B = mods
     wl = _spectra_wl(inputs, steps=4)
     wl.dt = 0.4
-    say("[lp] tracers + spectra, 16^3, float64 tiled kernel, sort every 2 steps")
-    run = driver.Run(wl, prec=B.PL_F64, algo=B.PL_ALGO_TILED, tile=(4, 4, 4), spectra=True)
+    say(f"[lp] tracers + spectra, 16^3, float64 {algo} kernel, sort every 2 steps")
+    if algo == "tiled":
+        kw = dict(algo=B.PL_ALGO_TILED)
+    else:
+        kw = dict(algo=B.PL_ALGO_RUNS, key_mode=B.PL_KEY_TILE_RUN, block=512)
+    run = driver.Run(wl, prec=B.PL_F64, tile=(4, 4, 4), spectra=True, **kw)
     for s in range(wl.steps):
         if s % 2 == 0:
             run.sort()
