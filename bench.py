@@ -56,6 +56,9 @@ def kernel_name(cfg, B):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_runs_f32_turbulent128_traffic.json")
 INSTR_FILE = os.path.join(ROOT, "profiles", "k_runs_f32_turbulent128_instructions.json")
+LDS_FILE = os.path.join(ROOT, "profiles", "k_runs_f32_turbulent128_lds.json")
+# LDS peak: 256 CUs x 128 bytes per clock at 2.4 GHz
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
 ERR_FILE = os.path.join(ROOT, "profiles", "f32_error_table_turbulent32.json")
 
 
@@ -475,6 +478,20 @@ def main():
                         "bank_conflict_ms_per_cu": ins["lds_conflict_ms_per_cu"],
                         "bank_conflict_frac": ins["lds_conflict_ms_per_cu"] / head["kernel_ms"]},
             }
+    # LDS occupancy and bytes per launch from the committed counters of the
+    # same kernel source; the bandwidth against this run's kernel time
+    if os.path.exists(LDS_FILE):
+        with open(LDS_FILE) as fh:
+            ld = json.load(fh)
+        from paper_2602_23434_amd import profiling
+        if ld.get("src_digest") == src_digest() and ld.get("config") == profiling.workload_config():
+            lds_tbs = ld["lds_bytes"] / (head["kernel_ms"] * 1e-3) / 1e12
+            secondary = dict(secondary or {})
+            secondary["lds"] = dict(secondary.get("lds", {}))
+            secondary["lds"].update({"busy_frac": ld["lds_util"],
+                                     "bank_conflict_share_of_busy": ld["bank_conflict_share_of_active"],
+                                     "bytes_per_launch": ld["lds_bytes"], "achieved_TBs": lds_tbs,
+                                     "peak_TBs": LDS_PEAK_TBS, "bw_frac": lds_tbs / LDS_PEAK_TBS})
     # float32 error table of the same kernel sources (written by the whole-grid
     # parity test of the benchmarked variant)
     error_table = None

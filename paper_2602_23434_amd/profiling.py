@@ -23,6 +23,14 @@ summaries kept beside the sources.
         `rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT`
         run of the same workload) as JSON.
 
+    python -m paper_2602_23434_amd.profiling lds LDS_A_CSV LDS_B_CSV AGENT_CSV COMMAND
+        LDS occupancy and bytes per launch of the run kernel as JSON, from a
+        `--pmc SQ_LDS_IDX_ACTIVE SQ_LDS_BANK_CONFLICT SQ_BUSY_CU_CYCLES GRBM_GUI_ACTIVE`
+        run and a `--pmc SQ_INSTS_LDS_LOAD_BANDWIDTH SQ_INSTS_LDS_STORE_BANDWIDTH
+        SQ_INSTS_LDS_ATOMIC_BANDWIDTH GRBM_GUI_ACTIVE` run of the same workload
+        (AGENT_CSV: rocprofv3's agent_info.csv of either run, for the CU and
+        XCD counts).
+
 FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch.  The JSON carries
 the digest of the kernel sources, so a reader can tell whether the figures
 still describe the built kernel.
@@ -194,6 +202,68 @@ def instructions(sq_csv, command):
     }
 
 
+# LDS: 128 bytes per clock per CU (32 banks of 4 bytes)
+LDS_BYTES_PER_CLK = 128
+
+
+def _kernel_means(path):
+    vals, name = {}, None
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Kernel_Name"].startswith("void pl::k_runs<"):
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+                name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+    return {k: sum(v) / len(v) for k, v in vals.items()}, {k: len(v) for k, v in vals.items()}, name
+
+
+def _gpu_agent(path):
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Agent_Type") == "GPU":
+                return int(r["Cu_Count"]), int(r["Num_Xcc"])
+    raise RuntimeError("no GPU agent in " + path)
+
+
+def lds(a_csv, b_csv, agent_csv, command):
+    """LDS occupancy of the run kernel (cycles the LDS serves indexed
+    operations over the launch's cycles on every CU) and its LDS bytes per
+    launch against what 128 bytes per clock per CU would move in the same
+    cycles.  GRBM_GUI_ACTIVE is summed over the XCDs in the CSV; one XCD's
+    count is the launch's length in clocks."""
+    ma, na, name = _kernel_means(a_csv)
+    mb, nb, name2 = _kernel_means(b_csv)
+    need_a = ("SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT", "GRBM_GUI_ACTIVE")
+    need_b = ("SQ_INSTS_LDS_LOAD_BANDWIDTH", "SQ_INSTS_LDS_STORE_BANDWIDTH", "SQ_INSTS_LDS_ATOMIC_BANDWIDTH",
+              "GRBM_GUI_ACTIVE")
+    if not all(k in ma for k in need_a) or not all(k in mb for k in need_b) or name != name2:
+        raise RuntimeError(f"missing counters or different kernels: {sorted(ma)} {sorted(mb)} {name} {name2}")
+    cus, xcc = _gpu_agent(agent_csv)
+    clk_a = ma["GRBM_GUI_ACTIVE"] / xcc
+    clk_b = mb["GRBM_GUI_ACTIVE"] / xcc
+    load = mb["SQ_INSTS_LDS_LOAD_BANDWIDTH"] * 64
+    store = mb["SQ_INSTS_LDS_STORE_BANDWIDTH"] * 64
+    atomic = mb["SQ_INSTS_LDS_ATOMIC_BANDWIDTH"] * 64
+    total = load + store + atomic
+    return {
+        "kernel": name,
+        "src_digest": src_digest(),
+        "config": workload_config(),
+        "launches": na["SQ_LDS_IDX_ACTIVE"],
+        "cu_count": cus,
+        "xcc_count": xcc,
+        "launch_clocks": clk_a,
+        "lds_active_cycles_per_cu": ma["SQ_LDS_IDX_ACTIVE"] / cus,
+        "lds_util": ma["SQ_LDS_IDX_ACTIVE"] / (clk_a * cus),
+        "bank_conflict_share_of_active": ma["SQ_LDS_BANK_CONFLICT"] / ma["SQ_LDS_IDX_ACTIVE"],
+        "lds_load_bytes": load,
+        "lds_store_bytes": store,
+        "lds_atomic_bytes": atomic,
+        "lds_bytes": total,
+        "lds_bw_frac": total / (LDS_BYTES_PER_CLK * cus * clk_b),
+        "command": command,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -212,6 +282,11 @@ def main(argv=None):
     i = sub.add_parser("instructions")
     i.add_argument("sq_csv")
     i.add_argument("command")
+    ld = sub.add_parser("lds")
+    ld.add_argument("a_csv")
+    ld.add_argument("b_csv")
+    ld.add_argument("agent_csv")
+    ld.add_argument("command")
     a = ap.parse_args(argv)
     if a.cmd == "workload":
         workload(a.steps)
@@ -223,6 +298,8 @@ def main(argv=None):
             sys.stdout.write(split_md(a.db, kern, parts))
     elif a.cmd == "instructions":
         print(json.dumps(instructions(a.sq_csv, a.command), indent=1))
+    elif a.cmd == "lds":
+        print(json.dumps(lds(a.a_csv, a.b_csv, a.agent_csv, a.command), indent=1))
     else:
         print(json.dumps(traffic(a.fetch_csv, a.write_csv, a.command), indent=1))
 

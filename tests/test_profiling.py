@@ -61,3 +61,34 @@ def test_instruction_ceilings(tmp_path):
     # 3e8 wave instructions x 4 cycles over 1024 SIMDs at 2.4 GHz
     assert t["valu_floor_ms"] == pytest.approx(3.0e8 * 4 / (1024 * 2.4e9) * 1e3)
     assert t["lds_conflict_ms_per_cu"] == pytest.approx(1.0e8 / 256 / 2.4e9 * 1e3)
+
+
+def _write_many(path, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        for i, (name, counter, val) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i + 1, "Grid_Size": 256, "Kernel_Name": name, "Counter_Name": counter,
+                        "Counter_Value": val})
+
+
+def test_lds_occupancy_and_bandwidth(tmp_path):
+    a, b, ag = tmp_path / "a.csv", tmp_path / "b.csv", tmp_path / "agent.csv"
+    # 4 CUs on 2 XCDs; the launch lasts 1000 clocks (GRBM_GUI_ACTIVE summed over the XCDs)
+    _write_many(a, [(RUNK, "SQ_LDS_IDX_ACTIVE", 2000.0), (RUNK, "SQ_LDS_BANK_CONFLICT", 500.0),
+                    (RUNK, "GRBM_GUI_ACTIVE", 2000.0), (COPY, "SQ_LDS_IDX_ACTIVE", 7.0)])
+    _write_many(b, [(RUNK, "SQ_INSTS_LDS_LOAD_BANDWIDTH", 3000.0), (RUNK, "SQ_INSTS_LDS_STORE_BANDWIDTH", 200.0),
+                    (RUNK, "SQ_INSTS_LDS_ATOMIC_BANDWIDTH", 800.0), (RUNK, "GRBM_GUI_ACTIVE", 2000.0)])
+    with open(ag, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Agent_Type", "Cu_Count", "Num_Xcc"])
+        w.writeheader()
+        w.writerow({"Agent_Type": "CPU", "Cu_Count": 16, "Num_Xcc": 1})
+        w.writerow({"Agent_Type": "GPU", "Cu_Count": 4, "Num_Xcc": 2})
+    t = profiling.lds(str(a), str(b), str(ag), "cmd")
+    assert t["cu_count"] == 4 and t["xcc_count"] == 2 and t["launch_clocks"] == 1000.0
+    assert t["lds_util"] == pytest.approx(2000.0 / (1000.0 * 4))
+    assert t["bank_conflict_share_of_active"] == pytest.approx(0.25)
+    assert t["lds_bytes"] == pytest.approx(4000.0 * 64)
+    # 4 CUs x 128 bytes per clock x 1000 clocks
+    assert t["lds_bw_frac"] == pytest.approx(4000.0 * 64 / (128 * 4 * 1000.0))
+    assert t["src_digest"] == profiling.src_digest()
