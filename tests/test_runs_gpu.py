@@ -152,7 +152,7 @@ def test_runs_table_exact(mods, prec, key):
     for n, npart, tile in ((32, 8 * 32 ** 3 - 37, (8, 8, 8)), (16, 1, (4, 4, 4)), (16, 3001, (16, 8, 2)),
                            (16, 20000, (4, 4, 4)), (16, 40 * 16 ** 3 + 5, (8, 8, 8)),
                            (16, 40 * 16 ** 3 + 5, (16, 8, 8)), (32, -1, (4, 4, 4)), (32, -2, (4, 4, 4)),
-                           (32, -2, (8, 8, 8))):
+                           (32, -2, (8, 8, 8)), (24, 5 * 24 ** 3 + 3, (6, 4, 3))):
         say(f"[runs] run table {prec} key {key} n={n} np={npart} tile={tile}")
         split = npart < 0 and tile == (4, 4, 4)
         if npart < 0:
@@ -212,6 +212,48 @@ def test_runs_turbulent_fp64(mods):
     _assert_runs_kernel(run, B)
     _check_item(run, 0, ores[0], wl, X_TOL, U_TOL, M_TOL)
     run.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_runs_tile_not_power_of_two(mods, prec):
+    """A 6x4x3 tile (72 cells: tile and cell indices by division, rows
+    swizzled in groups of four) on a 24^3 box, sorted every 2 of 6 steps:
+    float64 against the oracle within the parity tolerances; float32 per-id
+    states bit-identical to the tiled kernel on the same tile and deposits
+    within 2e-6 of its largest value."""
+    oracle, driver, inputs, B = mods
+    say(f"[runs] {prec} tile (6, 4, 3) on 24^3, 6 steps, sort every 2")
+    wl = inputs.turbulent_box(n=24, npart=8 * 24 ** 3 - 13, steps=6)
+    tile = (6, 4, 3)
+    if prec == "f64":
+        ores = oracle.run_workload(wl)
+        run, st = _run_gpu(driver, wl, wl.steps, True, sort_every=2, prec=B.PL_F64, algo=B.PL_ALGO_RUNS,
+                           tile=tile)
+        assert st == B.PL_OK
+        _assert_runs_kernel(run, B)
+        ex, eu, _ = _check_item(run, 0, ores[0], wl, X_TOL, U_TOL, M_TOL)
+        say(f"  max |dx| {ex:.3e} cells, max |du|/max(|u|, sigma) {eu:.3e}")
+        run.close()
+        return
+    res = {}
+    for algo in (B.PL_ALGO_TILED, B.PL_ALGO_RUNS):
+        kmode = B.PL_KEY_TILE_CELL if algo == B.PL_ALGO_TILED else B.PL_KEY_TILE_RUN
+        run, st = _run_gpu(driver, wl, wl.steps, True, sort_every=2, prec=B.PL_F32_OFFSET, algo=algo, tile=tile,
+                           key_mode=kmode)
+        assert st == B.PL_OK
+        if algo == B.PL_ALGO_RUNS:
+            _assert_runs_kernel(run, B)
+        raw = run.raw(0)
+        ids = raw["id"].astype(np.int64)
+        res[algo] = ({k: _cmp.by_id(np.stack(v) if isinstance(v, list) else v, ids) for k, v in raw.items()
+                      if k in ("x", "u", "cell")}, run.moments(0))
+        run.close()
+    (sa, ma), (sb, mb) = res[B.PL_ALGO_TILED], res[B.PL_ALGO_RUNS]
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    for k in ma:
+        va, vb = np.asarray(ma[k]), np.asarray(mb[k])
+        assert np.abs(va - vb).max() <= 2e-6 * np.abs(va).max(), k
 
 
 def test_runs_f32_error_table(mods):
