@@ -210,14 +210,16 @@ def gyration_2d(npart=4096, n=32, steps=10, seed=SEED_P + 0):
 
 
 def turbulent_box(n=128, npart=1 << 24, steps=20, k=1, sigma_v=0.05):
-    """3D periodic box with turbulent E, B and uniformly placed Maxwellian particles."""
-    nn = (n, n, n)
+    """3D periodic box with turbulent E, B and uniformly placed Maxwellian
+    particles; n is the cell count per dimension, or three counts."""
+    nn = tuple(int(v) for v in n) if isinstance(n, (tuple, list)) else (n, n, n)
     flds = turbulent_fields(nn, SEED_B + k, SEED_V + k)
     rng = np.random.default_rng(SEED_P + k)
     x = uniform_positions(rng, npart, nn, 3)
     u = maxwellian_u(rng, npart, sigma_v)
     box = Box(ndim=3, n=nn, fields=flds)
-    return Workload(name=f"turbulent {n}^3, {npart} particles", boxes=[box],
+    shape = f"{n}^3" if nn[0] == nn[1] == nn[2] else "x".join(str(v) for v in nn)
+    return Workload(name=f"turbulent {shape}, {npart} particles", boxes=[box],
                     species=[Species("lorentz")], items=[Item(0, 0, make_particles(x, u))],
                     dt=0.05, steps=steps)
 
