@@ -325,16 +325,18 @@ def spectra_box(n=160, ppc=4, nb=128, steps=10, k=5, divu_rms=0.1, dt=0.05):
     cell by cell, each carrying nb spectral points initialised to the power
     law of powerlaw_spectrum; turbulent B and gas velocity, and a random
     four-divergence field (rms divu_rms) for the adiabatic term.  The spectra
-    are returned as one (nb,) template (every particle starts with it)."""
-    nn = (n, n, n)
+    are returned as one (nb,) template (every particle starts with it).  n is
+    the cell count per dimension, or three counts."""
+    nn = tuple(int(v) for v in n) if isinstance(n, (tuple, list)) else (n, n, n)
     flds = turbulent_fields(nn, SEED_B + k, SEED_V + k)
     flds["divu"] = scalar_field(nn, SEED_V + 100 + k, divu_rms)
     rng = np.random.default_rng(SEED_P + k)
-    npart = ppc * n ** 3
+    npart = ppc * nn[0] * nn[1] * nn[2]
     x = per_cell_positions(rng, ppc, nn)
     box = Box(ndim=3, n=nn, fields=flds)
     eng, chi = powerlaw_spectrum(nb)
-    return Workload(name=f"spectra {n}^3, {npart} particles, {nb} bins", boxes=[box],
+    shape = f"{n}^3" if nn[0] == nn[1] == nn[2] else "x".join(str(v) for v in nn)
+    return Workload(name=f"spectra {shape}, {npart} particles, {nb} bins", boxes=[box],
                     species=[Species("tracer")], items=[Item(0, 0, make_particles(x, np.zeros((3, npart))))],
                     dt=dt, steps=steps, notes={"eng0": eng, "chi0": chi})
 

@@ -60,12 +60,13 @@ def _oracle_spectra(oracle, wl, x, steps):
     return eng, chi
 
 
-@pytest.mark.parametrize("prec,shape", [("f64", "tsc"), ("f32", "tsc"), ("f64", "cic")])
-def test_spectra_vs_oracle(mods, prec, shape):
+@pytest.mark.parametrize("prec,shape,n", [("f64", "tsc", 16), ("f32", "tsc", 16), ("f64", "cic", 16),
+                                          ("f64", "tsc", (20, 12, 16)), ("f32", "tsc", (20, 12, 16))])
+def test_spectra_vs_oracle(mods, prec, shape, n):
     oracle, driver, inputs, B = mods
-    wl = _spectra_wl(inputs, shape=shape)
+    wl = _spectra_wl(inputs, n=n, shape=shape)
     npart = wl.items[0].particles.n
-    say(f"[lp] spectra {prec} {shape}: 16^3, {npart} particles x 128 points, 3 steps")
+    say(f"[lp] spectra {prec} {shape}: {wl.boxes[0].n}, {npart} particles x 128 points, 3 steps")
     p = B.PL_F64 if prec == "f64" else B.PL_F32_OFFSET
     run = driver.Run(wl, prec=p, algo=B.PL_ALGO_PLAIN, spectra=True)
     for _ in range(wl.steps):
@@ -128,21 +129,23 @@ def test_spectra_move_with_sort_and_push(mods, algo):
     run.close()
 
 
+@pytest.mark.parametrize("n", [16, (20, 12, 16)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_boundary_compaction_exact(mods, prec):
-    """Particles placed over the whole box, sorted by tile, one spectral step,
-    then x and z opened with two ghost layers: the GPU deletes and compacts
+def test_boundary_compaction_exact(mods, prec, n):
+    """Particles placed over the whole box (16^3, or 20x12x16 so that a
+    swapped dimension shows), sorted by tile, one spectral step, then x and z
+    opened with two ghost layers: the GPU deletes and compacts
     exactly as the oracle's holes-and-fillers algorithm does on the oracle's
     own sorted state (stable tile sort, spectra at the same positions), every
     array including the spectral rows moving with its particle; the item is
     unsorted afterwards."""
     oracle, driver, inputs, B = mods
     tile = (4, 4, 4)
-    wl = _spectra_wl(inputs, n=16, ppc=4, nb=16, steps=1)
+    wl = _spectra_wl(inputs, n=n, ppc=4, nb=16, steps=1)
     box = wl.boxes[0]
     p = B.PL_F64 if prec == "f64" else B.PL_F32_OFFSET
     n0 = wl.items[0].particles.n
-    say(f"[lp] boundary {prec}: 16^3 open in x and z, ghost 2, {n0} particles")
+    say(f"[lp] boundary {prec}: {box.n} open in x and z, ghost 2, {n0} particles")
     run = driver.Run(wl, prec=p, algo=B.PL_ALGO_TILED, tile=tile, spectra=True)
     run.sort()
     run.spectra(cr=CR, u_rad=U_RAD, ub=UB)            # rows now differ from particle to particle
