@@ -38,7 +38,7 @@ SEED_B, SEED_V, SEED_P = 1000, 2000, 3000
 
 
 def _solenoidal_modes(n, seed, kmax_frac=0.25, slope=-11.0 / 6.0):
-    """Random divergence-free vector field on an n^3 periodic grid (rms not set)."""
+    """Random divergence-free vector field on an nx x ny x nz periodic grid (rms not set)."""
     rng = np.random.default_rng(seed)
     nx, ny, nz = n
     kx = np.fft.rfftfreq(nx, 1.0 / nx)
@@ -47,7 +47,7 @@ def _solenoidal_modes(n, seed, kmax_frac=0.25, slope=-11.0 / 6.0):
     KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
     k2 = KX * KX + KY * KY + KZ * KZ
     kmag = np.sqrt(k2)
-    kmax = kmax_frac * min(nx, ny, nz)
+    kmax = kmax_frac * min(v for v in n if v > 1)     # a 2D grid (nz = 1) keeps its in-plane modes
     live = (kmag >= 1.0) & (kmag <= kmax)
     amp = np.zeros_like(kmag)
     amp[live] = kmag[live] ** slope
@@ -195,6 +195,21 @@ def make_particles(x, u, weight=1.0):
     npart = x.shape[1]
     return Particles(x=np.ascontiguousarray(x), u=np.ascontiguousarray(u),
                      w=np.full(npart, float(weight)), id=np.arange(npart, dtype=np.uint64))
+
+
+def turbulent_2d(n=(48, 16), npart=6000, steps=6, k=7, sigma_v=0.05):
+    """2D periodic box (n[0] x n[1] cells) with turbulent in-plane fields and
+    uniformly placed Maxwellian particles (a non-square grid, so that a
+    swapped dimension shows)."""
+    nn = (int(n[0]), int(n[1]), 1)
+    flds = turbulent_fields(nn, SEED_B + k, SEED_V + k)
+    rng = np.random.default_rng(SEED_P + k)
+    x = uniform_positions(rng, npart, nn, 2)
+    u = maxwellian_u(rng, npart, sigma_v)
+    box = Box(ndim=2, n=nn, fields=flds)
+    return Workload(name=f"turbulent 2D {nn[0]}x{nn[1]}, {npart} particles", boxes=[box],
+                    species=[Species("lorentz")], items=[Item(0, 0, make_particles(x, u))],
+                    dt=0.05, steps=steps)
 
 
 def gyration_2d(npart=4096, n=32, steps=10, seed=SEED_P + 0):
