@@ -265,16 +265,20 @@ def test_rank_key_tile_not_power_of_two(mods, prec):
         assert np.abs(va - vb).max() <= rtol * np.abs(va).max(), k
 
 
+@pytest.mark.parametrize("nn,ppc", [((40, 24, 16), 8), ((1024, 8, 8), 2)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_non_cubic_box(mods, prec):
+def test_non_cubic_box(mods, prec, nn, ppc):
     """A 40x24x16 box (every extent different, so a swapped dimension
-    anywhere shows), sorted every 2 of 4 steps: float64 plain, tiled and
-    run-based kernels against the oracle; float32 tiled and run-based
-    kernels with per-id states bit-identical to the float32 plain kernel
-    and deposits within 2e-6 of its largest value."""
+    anywhere shows) and a 1024x8x8 box (the largest extent the float32
+    form's packed cell holds, particles wrapping from cell 1023 to 0),
+    sorted every 2 of 4 steps: float64 plain, tiled and run-based kernels
+    against the oracle; float32 tiled and run-based kernels with per-id
+    states bit-identical to the float32 plain kernel and deposits within
+    2e-6 of its largest value."""
     oracle, driver, inputs, B = mods
-    nn = (40, 24, 16)
-    wl = inputs.turbulent_box(n=nn, npart=8 * 40 * 24 * 16 - 7, steps=4)
+    wl = inputs.turbulent_box(n=nn, npart=ppc * nn[0] * nn[1] * nn[2] - 7, steps=4)
+    if nn[0] == 1024:
+        wl.dt = 1.0          # about 0.05 cells per step: a few dozen particles cross x = 1024
     p = B.PL_F64 if prec == "f64" else B.PL_F32_OFFSET
     # the run kernel's float64 LDS tiles fit 8x8x4 tiles, its float32 ones 8^3
     configs = ((B.PL_ALGO_PLAIN, None, B.PL_KEY_TILE), (B.PL_ALGO_TILED, (8, 8, 4), B.PL_KEY_TILE_CELL),
@@ -291,6 +295,11 @@ def test_non_cubic_box(mods, prec):
             assert stats[4] > 0 and stats[5] == 0, stats
         if prec == "f64":
             _check_item(run, 0, ores[0], wl, X_TOL, U_TOL, M_TOL)
+            if nn[0] == 1024 and algo == B.PL_ALGO_PLAIN:
+                x0 = wl.items[0].particles.x[0]
+                crossed = int(np.count_nonzero(np.abs(ores[0]["x"][0] - x0) > nn[0] / 2))
+                say(f"  {crossed} particles crossed x = {nn[0]}")
+                assert crossed > 0
         else:
             raw = run.raw(0)
             ids = raw["id"].astype(np.int64)
