@@ -34,6 +34,30 @@ def test_turbulent_fields_properties():
     assert np.abs(hat[km > 8.0 + 1e-9]).max() < 1e-9 * np.abs(hat).max()
 
 
+def test_turbulent_fields_2d_and_non_cubic():
+    """On a 48x16 2D grid and a 40x24x16 box the fields keep their rms, stay
+    divergence-free, and hold power only at 1 <= |m| <= (smallest extent
+    above one) / 4."""
+    for n in ((48, 16, 1), (40, 24, 16)):
+        f = inputs.turbulent_fields(n, inputs.SEED_B + 7, inputs.SEED_V + 7)
+        B, vg = f["B"], f["vg"]
+        assert B.shape == (3, n[2], n[1], n[0])
+        dB = B.copy()
+        dB[2] -= 1.0
+        assert abs(math.sqrt(np.mean((dB * dB).sum(axis=0))) - 0.5) < 1e-12
+        assert abs(math.sqrt(np.mean((vg * vg).sum(axis=0))) - 0.1) < 1e-12
+        kz, ky, kx = np.meshgrid(*[np.fft.fftfreq(a, 1.0 / a) for a in (n[2], n[1], n[0])], indexing="ij")
+        km = np.sqrt(kx ** 2 + ky ** 2 + kz ** 2)
+        kmax = 0.25 * min(a for a in n if a > 1)
+        for fld in (B, vg):
+            hat = [np.fft.fftn(fld[c]) for c in range(3)]
+            div = kx * hat[0] + ky * hat[1] + kz * hat[2]
+            mag = km * np.sqrt(sum(np.abs(h) ** 2 for h in hat))
+            assert np.abs(div).max() <= 1e-12 * mag.max()
+        hat = np.fft.fftn(dB[0])
+        assert np.abs(hat[(km > kmax + 1e-9) | (km < 1.0 - 1e-9)]).max() < 1e-9 * np.abs(hat).max()
+
+
 def test_generator_is_deterministic():
     a = inputs.turbulent_box(n=16, npart=1000)
     b = inputs.turbulent_box(n=16, npart=1000)
