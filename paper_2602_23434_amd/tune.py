@@ -89,6 +89,8 @@ def candidates(n, prec):
         yield B.PL_ALGO_RUNS, tile, block, key, every
     # reference: the tiled kernel with the rank-interleaved key
     tile = (8, 8, 8) if prec == B.PL_F32_OFFSET else (8, 8, 4)
+    if any(n % t for t in tile):
+        return
     for every in CADENCES:
         yield B.PL_ALGO_TILED, tile, 512, B.PL_KEY_TILE_RANK, every
 
@@ -105,7 +107,9 @@ def tune(n=128, ppc=8, steps=32, prec=B.PL_F32_OFFSET, log=print, batched=False)
     best = None
     results = []
     # one untimed pass first, so the first candidate does not pay for clocks ramping up
-    first = next(iter(candidates(n, prec)))
+    first = next(iter(candidates(n, prec)), None)
+    if first is None:
+        raise ValueError(f"no candidate tile divides a box of {n} cells per side: {TILES}")
     time_candidate(wl, prec, first[0], first[1], first[2], first[3], first[4], steps, torch, reps=1,
                    channels=channels)
     for algo, tile, block, key, every in candidates(n, prec):
