@@ -432,6 +432,8 @@ def main():
         paths.append(("f32_tiled", BC.F32_TILED, every, args.reps))
     if not args.no_fp64:
         paths.append(("f64_plain", BC.F64_PLAIN, 0, 1))
+        if not args.no_tiled:
+            paths.append(("f64_tiled", BC.F64_TILED, every64, args.reps))
         paths.append(("f64_runs", BC.run_kwargs(f64_cfg), every64, args.reps))
     for name, cfg, ev_every, reps in paths:
         log(f"[bench] path {name}: setup")
@@ -532,7 +534,8 @@ def main():
         "secondary_ceilings": secondary,
         "error_table": error_table,
     }
-    for name, key in (("f32_tiled", "fp32_tiled"), ("f64_plain", "fp64_plain"), ("f64_runs", "fp64_runs")):
+    for name, key in (("f32_tiled", "fp32_tiled"), ("f64_plain", "fp64_plain"), ("f64_tiled", "fp64_tiled"),
+                      ("f64_runs", "fp64_runs")):
         if name in results:
             r = results[name]
             out[key] = {"value": r["updates_per_s"], "ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
@@ -540,6 +543,8 @@ def main():
                         "achieved_GBs": r["alg_bytes"] / (r["kernel_ms"] * 1e-3) / 1e9}
     if "f64_plain" in results:
         out["speedup_f32_over_f64_plain"] = head["updates_per_s"] / results["f64_plain"]["updates_per_s"]
+    if "f64_tiled" in results:
+        out["speedup_f32_over_f64_tiled"] = head["updates_per_s"] / results["f64_tiled"]["updates_per_s"]
     if "f64_runs" in results:
         out["speedup_f32_over_f64_runs"] = head["updates_per_s"] / results["f64_runs"]["updates_per_s"]
     if not args.no_boundary:

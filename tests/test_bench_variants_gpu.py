@@ -113,6 +113,48 @@ def test_bench_variant_f32_whole_grid(mods, turb32):
     run.close()
 
 
+def _by_id(a, ids):
+    return a[:, np.argsort(ids)]
+
+
+def test_bench_variant_tiled_whole_grid(mods, turb32):
+    """The benchmark's tiled paths (one thread per particle, rank-interleaved
+    sort): float64 on 8x8x4 tiles and the float32 form on 8^3 tiles, both with
+    rho+J+F, 20 steps with a sort every 8 steps.  Float64: every particle and
+    cell against the oracle at the float64 bounds.  Float32: the error table
+    within the frozen bounds, and every particle's state bit-identical (per id)
+    to the run-based float32 kernel's, which adds the same terms in the same
+    order."""
+    oracle, driver, inputs, B = mods
+    from paper_2602_23434_amd import benchcfg as BC
+    wl, ores = turb32
+    say("[variants] f64 tiled kernel, 8x8x4 tiles, rho J F, 32^3, 20 steps, sort every 8, vs oracle")
+    run = _bench_run(driver, B, wl, BC.F64_TILED, BC.SORT_EVERY)
+    ex, eu, errs = _check_item(run, 0, ores[0], wl, X_TOL, U_TOL, M_TOL, eng=False)
+    assert set(errs) == {"rho", "J0", "J1", "J2", "F0", "F1", "F2"}, errs.keys()
+    say(f"  x {ex:.2e} u {eu:.2e} " + " ".join(f"{k}:{v[0]:.1e}" for k, v in errs.items()))
+    run.close()
+
+    say("[variants] f32 tiled kernel, 8^3 tiles, rho J F, 32^3, 20 steps, sort every 8, vs oracle and run kernel")
+    run = _bench_run(driver, B, wl, BC.F32_TILED, BC.SORT_EVERY)
+    tx, tu, tid, _ = run.state(0)
+    table = _cmp.state_error_stats(tx, tu, tid, ores[0]["x"], ores[0]["u"], wl.boxes[0].n, 3)
+    merr = _cmp.moment_errors(run.moments(0), ores[0]["moments"], ores[0]["abs"])
+    run.close()
+    for k, (mx, rms) in table.items():
+        say(f"  {k:4s} max {mx:.3e} rms {rms:.3e}")
+    for k, (mx, rms, rel) in merr.items():
+        say(f"  {k:4s} max/A_c {mx:.3e} rms/A_c {rms:.3e}")
+    bad = _cmp.check_fp32_table(table, merr)
+    assert not bad, bad
+    run = _bench_run(driver, B, wl, BC.F32_RUNS, BC.SORT_EVERY)
+    rx, ru, rid, _ = run.state(0)
+    run.close()
+    assert np.array_equal(np.sort(tid), np.sort(rid))
+    assert np.array_equal(_by_id(tx, tid), _by_id(rx, rid))
+    assert np.array_equal(_by_id(tu, tid), _by_id(ru, rid))
+
+
 # ---------------------------------------------------------------- unsorted items
 
 def _snapshot(run):

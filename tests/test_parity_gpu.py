@@ -606,7 +606,7 @@ def _sampled_cells_check(oracle, wl, gm, steps, ncells=48, seed=12, margin=2.0):
     return worst
 
 
-@pytest.mark.parametrize("path", ["f32_runs", "f32_tiled", "f64_plain"])
+@pytest.mark.parametrize("path", ["f32_runs", "f32_tiled", "f64_plain", "f64_tiled"])
 def test_fullsize_sampled(mods, path):
     """128^3 turbulent box, 2^24 particles, 20 steps, in the launch
     configuration the benchmark times (sorted paths re-sort every
@@ -621,7 +621,7 @@ def test_fullsize_sampled(mods, path):
     say(f"[parity] full size 128^3, 2^24 particles, 20 steps, {path} (bench configuration)")
     wl = inputs.turbulent_box(n=BC.TURB_N, npart=BC.TURB_NP, steps=20)
     cfg = {"f32_runs": BC.headline(), "f32_tiled": dict(BC.F32_TILED, sort_every=BC.SORT_EVERY),
-           "f64_plain": BC.F64_PLAIN}[path]
+           "f64_plain": BC.F64_PLAIN, "f64_tiled": dict(BC.F64_TILED, sort_every=BC.SORT_EVERY)}[path]
     run = driver.Run(wl, **BC.run_kwargs(cfg))
     sorted_path = cfg["algo"] != B.PL_ALGO_PLAIN
     for s in range(wl.steps):
@@ -652,7 +652,7 @@ def test_fullsize_sampled(mods, path):
     dx = np.abs(_cmp.min_image(gxs - x, 128)).max()
     du = (np.sqrt(((gus - u) ** 2).sum(axis=0)) / np.maximum(np.sqrt((u * u).sum(axis=0)), 0.05)).max()
     say(f"  sampled max |dx| {dx:.3e} cells, max |du|/max(|u|,sigma) {du:.3e}")
-    f64 = path == "f64_plain"
+    f64 = path.startswith("f64")
     if f64:
         assert dx <= X_TOL and du <= U_TOL
     else:
