@@ -18,7 +18,9 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liborc.so")
+# ORC_LIB names another build of orc.c to load instead (the mutation tests
+# load copies with a planted mistake this way)
+LIB_PATH = os.environ.get("ORC_LIB") or os.path.join(HERE, "liborc.so")
 
 CIC, TSC = 1, 2
 LORENTZ, DUST, TRACER = 0, 1, 2
