@@ -13,7 +13,15 @@ mutant and pass on an unmodified copy built the same way:
   F_p = q w (E_p + vbar x B_p));
 * the deposit taken at the old position x^n instead of x^{n+1}, or the
   current from the momentum u instead of the velocity v = u / gamma (pinned by
-  the single-particle deposit at the closed-form new position, P4, P8).
+  the single-particle deposit at the closed-form new position, P4, P8);
+* the spectral update (Sec. 2): chi scaled by den instead of den^2, the
+  laboratory instead of the proper time step, |B| instead of |B|^2 in the
+  magnetic energy density (pinned by the characteristics, number
+  conservation, cooling cutoff and proper-time pins);
+* the compaction and boundary flags (Sec. 3.2): fillers taken from the end of
+  the array backwards instead of in index order, the upper open face one cell late
+  (pinned by the holes-and-fillers properties, the flags and the exact
+  outflow count).
 
 Nothing here touches the GPU or the HIP library.
 """
@@ -49,6 +57,16 @@ MUTANTS = {
          "double xp[3] = {mu[16 * p + 8], mu[16 * p + 9], mu[16 * p + 10]};", 0),
         ("const double *mp = mu + 8 * p;", "const double *mp = mu + 16 * p;", 0),
     ], "time_level"),
+    # spectral update (Sec. 2, Eqs. 2-6)
+    "spectra_chi_den_unsquared": ([("chi[p * nb + i] * den * den / E;", "chi[p * nb + i] * den / E;", 0)],
+                                  "spectra_"),
+    "spectra_lab_time": ([("double dtau = dt / gamma_g;", "double dtau = dt;", 0)], "spectra_"),
+    "spectra_b_not_squared": ([("par->ub * dot(Bp, Bp)", "par->ub * sqrt(dot(Bp, Bp))", 0)], "spectra_"),
+    # holes-and-fillers compaction (Sec. 3.2)
+    "compact_fillers_reversed": ([("for (long p = keep; p < np; ++p)", "for (long p = np - 1; p >= keep; --p)", 0)],
+                                 "compaction"),
+    "outside_upper_face": ([("cell >= (double)(b->n[d] - ghost)", "cell > (double)(b->n[d] - ghost)", 0)],
+                           "outside_flags or outflow"),
 }
 
 SELECT_ALL = " or ".join(sorted({sel for _, sel in MUTANTS.values()}))
@@ -76,7 +94,8 @@ def _build(tmp, name, text):
 def _pins(so, select):
     env = dict(os.environ, ORC_LIB=so, OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", select],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_spectra_boundary.py"), "-k", select],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     return r.returncode, r.stdout[-2000:]
 
