@@ -396,7 +396,11 @@ pl_status pl_part_boundary(pl_ctx *ctx, pl_item *items, int nitems, const pl_bou
  * (nullable; k * nbins float64, particle-major, when the set has spectra).
  * cap is the capacity of the caller's arrays (in particles); n + k must not
  * exceed cap or max_np.  Sets item->p.n to n + k and marks the item unsorted
- * (PL_ENOTSORTED until the next pl_part_sort).  Asynchronous.
+ * (PL_ENOTSORTED until the next pl_part_sort).  Asynchronous.  Errors: a null
+ * context, item, x or u, k < 0, n + k above cap or max_np, a null or
+ * misaligned array the set needs (eng and chi when it has spectra), or an
+ * item the context rejects: PL_EINVAL, before any device work; a failed
+ * launch: PL_EHIP.  k = 0 is a no-op.
  */
 pl_status pl_part_inject(pl_ctx *ctx, pl_item *item, int64_t k, const double *x[3], const double *u[3],
                          const double *w, const uint64_t *id, const double *eng, const double *chi, int64_t cap);
